@@ -1,0 +1,194 @@
+"""Aggregation AMG hierarchy, V-cycle and PCG (oracle, test infrastructure only).
+
+* Galerkin coarse operators A_{l+1} = P_l^T A_l P_l (Section 2, first display).
+* Piecewise-constant P from fixed 2x2x2 box aggregates of the structured
+  grid (entries 1.0; a dimension of extent 1 is not coarsened, an odd extent
+  leaves a last aggregate one cell wide).  Problems stacked along z
+  (``nbatch`` > 1) are aggregated separately.
+* Coarsening continues while a level has more than ``max_coarse`` rows per
+  problem; the coarsest level is solved by dense Cholesky (scipy cho_factor /
+  cho_solve), one factor per stacked problem.
+* V-cycle of eq. (amg): pre-smoothing with p_k(M^{-1}A) from zero, residual
+  restriction, recursion, prolongation, post-smoothing with the same
+  polynomial (M is diagonal and p_k(M^{-1}A) is A-self-adjoint, so the
+  M^{-T} of eq. (amg) is the same operator and the V-cycle is symmetric).
+* Preconditioned CG with x0 = 0 and the stopping test ||r_k||_2 <= rtol ||b||_2
+  on the recursively updated residual; an optional flexible (Polak-Ribiere)
+  beta for preconditioners that are not exactly fixed (the paper's runs use
+  a flexible CG, Section 4).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import polynomials as P
+from .smoothers import OPTCHEB1, OPTCHEB4, l1_diagonal, smooth
+
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    Minv: np.ndarray
+    grid: tuple  # per-problem (nx, ny, nz)
+    nbatch: int
+    P: sp.csr_matrix | None = None  # prolongation to this level from the next one
+
+
+@dataclass
+class Hierarchy:
+    levels: list = field(default_factory=list)
+    chol: list = field(default_factory=list)  # cho_factor per stacked problem on the coarsest level
+
+    @property
+    def L(self):
+        return len(self.levels) - 1
+
+
+def box_aggregates(grid, nbatch=1):
+    """Aggregate index of every fine row and the coarse per-problem grid.
+
+    Fine row (i, j, k) of problem p belongs to coarse cell (i//2, j//2, k//2)
+    of problem p (a dimension of extent 1 is kept); coarse rows are ordered
+    problem-major, then lexicographically.
+    """
+    nx, ny, nz = grid
+    cx = nx if nx == 1 else (nx + 1) // 2
+    cy = ny if ny == 1 else (ny + 1) // 2
+    cz = nz if nz == 1 else (nz + 1) // 2
+    i = np.arange(nx) if nx == 1 else np.arange(nx) // 2
+    j = np.arange(ny) if ny == 1 else np.arange(ny) // 2
+    k = np.arange(nz) if nz == 1 else np.arange(nz) // 2
+    agg1 = (i[None, None, :] + cx * j[None, :, None] + cx * cy * k[:, None, None]).ravel()
+    nc1 = cx * cy * cz
+    agg = np.concatenate([agg1 + p * nc1 for p in range(nbatch)])
+    return agg.astype(np.int64), (cx, cy, cz)
+
+
+def prolongator(agg, nc):
+    n = agg.size
+    return sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, nc))
+
+
+def build_hierarchy(A, grid, nbatch=1, max_coarse=4096):
+    """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse."""
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    H = Hierarchy()
+    g = tuple(grid)
+    if nbatch > 1:
+        g = (g[0], g[1], g[2] // nbatch)
+    H.levels.append(Level(A=A, Minv=l1_diagonal(A), grid=g, nbatch=nbatch))
+    while A.shape[0] // nbatch > max_coarse:
+        agg, gc = box_aggregates(g, nbatch)
+        nc = int(np.prod(gc)) * nbatch
+        if nc >= A.shape[0]:
+            raise ValueError("aggregation does not reduce the level")
+        Pm = prolongator(agg, nc)
+        Ac = (Pm.T @ A @ Pm).tocsr()
+        Ac.sort_indices()
+        H.levels[-1].P = Pm
+        A, g = Ac, gc
+        H.levels.append(Level(A=A, Minv=l1_diagonal(A), grid=g, nbatch=nbatch))
+    nL = A.shape[0] // nbatch
+    dense = A.toarray()
+    for p in range(nbatch):
+        blk = dense[p * nL:(p + 1) * nL, p * nL:(p + 1) * nL]
+        H.chol.append(sla.cho_factor(blk, lower=True))
+    return H
+
+
+def coarse_solve(H, b):
+    nb = H.levels[-1].nbatch
+    nL = b.size // nb
+    out = np.empty_like(b)
+    for p in range(nb):
+        out[p * nL:(p + 1) * nL] = sla.cho_solve(H.chol[p], b[p * nL:(p + 1) * nL])
+    return out
+
+
+def smoother_params(kind, k, beta=None):
+    """Default constants: the optimal beta table (OPTCHEB4) and a*_k (OPTCHEB1)."""
+    if kind == OPTCHEB4 and beta is None:
+        beta = P.optimal_beta(k)[0]
+    a = P.a_star(k) if kind == OPTCHEB1 else None
+    return beta, a
+
+
+def vcycle(H, r, kind, k, beta=None, level=0, betas_by_level=None):
+    """z = B r for the multiplicative V-cycle of eq. (amg).
+
+    ``beta`` is used on every level unless ``betas_by_level[l]`` is given
+    (per-level weights, used by the learned-beta variant).
+    """
+    if level == H.L:
+        return coarse_solve(H, r)
+    lv = H.levels[level]
+    bl = beta if betas_by_level is None else betas_by_level[level]
+    bl, a = smoother_params(kind, k, bl)
+    x = smooth(lv.A, lv.Minv, r, None, kind, k, bl, a)
+    res = r - lv.A @ x
+    rc = lv.P.T @ res
+    xc = vcycle(H, rc, kind, k, beta, level + 1, betas_by_level)
+    x = x + lv.P @ xc
+    x = smooth(lv.A, lv.Minv, r, x, kind, k, bl, a)
+    return x
+
+
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    iters: int
+    relres: float
+    history: list
+    converged: bool
+
+
+def pcg(A, b, precond, rtol=1e-8, maxit=1000, flexible=False):
+    """Preconditioned CG from x0 = 0; stops when ||r_k|| <= rtol ||b|| (recursive residual).
+
+    ``precond(r)`` returns z = B r.  Standard beta = (r_{k+1}, z_{k+1})/(r_k, z_k);
+    flexible beta = (z_{k+1}, r_{k+1} - r_k)/(r_k, z_k).
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.sqrt(np.dot(b, b))
+    if nb == 0.0:
+        return PCGResult(x, 0, 0.0, [0.0], True)
+    hist = [1.0]
+    z = precond(r)
+    p = z.copy()
+    rz = np.dot(r, z)
+    for it in range(1, maxit + 1):
+        q = A @ p
+        pq = np.dot(p, q)
+        alpha = rz / pq
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        rel = np.sqrt(np.dot(r, r)) / nb
+        hist.append(rel)
+        if rel <= rtol:
+            return PCGResult(x, it, rel, hist, True)
+        z = precond(r)
+        if flexible:
+            rz_new = np.dot(r, z)
+            beta = np.dot(z, r - r_old) / rz
+        else:
+            rz_new = np.dot(r, z)
+            beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    return PCGResult(x, maxit, hist[-1], hist, False)
+
+
+def amg_pcg(A, b, grid, kind, k, nbatch=1, max_coarse=4096, rtol=1e-8, maxit=1000, H=None,
+            flexible=False, beta=None):
+    """Set up the hierarchy (unless given) and solve A x = b with the V-cycle-preconditioned CG."""
+    if H is None:
+        H = build_hierarchy(A, grid, nbatch, max_coarse)
+    res = pcg(H.levels[0].A, b, lambda r: vcycle(H, r, kind, k, beta), rtol, maxit, flexible)
+    return res, H

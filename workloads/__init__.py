@@ -1,0 +1,285 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU library's tests.
+
+This module only builds *problem data*: sparse SPD matrices in CSR form,
+right-hand sides and random coefficient fields.  It holds none of the
+smoother / multigrid / Krylov arithmetic, so it may be imported by both the
+oracle and the GPU-side tests and benchmark without coupling them.
+
+Ordering is lexicographic, row = i + nx*j + nx*ny*k, with Dirichlet unknowns
+eliminated (only interior nodes are unknowns).  Within a row the column
+indices are strictly increasing.
+
+The workloads stand in for the paper's synthetic PDE test matrices (Poisson
+3D 7-point, Section 4; the paper measures on no external dataset).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from fractions import Fraction
+
+import numpy as np
+
+__all__ = [
+    "CSR",
+    "stencil_csr",
+    "poisson2d_5pt",
+    "poisson3d_7pt",
+    "q1_27pt",
+    "fv_diffusion",
+    "gaussian_random_field",
+    "rhs_uniform",
+    "stack_block_diagonal",
+    "config_problem",
+    "SEED_RHS",
+    "SEED_GRF",
+    "SEED_MLP",
+]
+
+# Seed bases: b uses default_rng(SEED_RHS + config number), the Gaussian
+# random field of problem p uses default_rng(SEED_GRF + p), the MLP initial
+# weights use default_rng(SEED_MLP).
+SEED_RHS = 1000
+SEED_GRF = 2000
+SEED_MLP = 3000
+
+
+@dataclass
+class CSR:
+    """Host CSR matrix: int32 row_ptr/col, float64 val, plus grid shape."""
+
+    n: int
+    row_ptr: np.ndarray  # int64 during assembly, int32 when stored (nnz < 2**31)
+    col: np.ndarray  # int32
+    val: np.ndarray  # float64
+    grid: tuple  # (nx, ny, nz)
+    nbatch: int = 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def stencil_csr(grid, offsets, values):
+    """Assemble a CSR matrix from a stencil on an (nx, ny, nz) interior grid.
+
+    ``offsets`` is a list of (dx, dy, dz); ``values[m]`` is either a scalar or
+    an array of shape (nz, ny, nx) giving the coefficient that row (i,j,k)
+    places on its neighbour (i+dx, j+dy, k+dz).  Neighbours outside the grid
+    are dropped (Dirichlet elimination).  Entries are stored even when their
+    value is exactly zero (the stencil pattern, not the values, fixes nnz).
+    """
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    order = sorted(range(len(offsets)), key=lambda m: (offsets[m][2], offsets[m][1], offsets[m][0]))
+    kk, jj, ii = np.meshgrid(np.arange(nz, dtype=np.int32), np.arange(ny, dtype=np.int32),
+                             np.arange(nx, dtype=np.int32), indexing="ij")
+    masks = []
+    counts = np.zeros((nz, ny, nx), dtype=np.int32)
+    for m in order:
+        dx, dy, dz = offsets[m]
+        mk = ((ii + dx >= 0) & (ii + dx < nx) & (jj + dy >= 0) & (jj + dy < ny)
+              & (kk + dz >= 0) & (kk + dz < nz))
+        masks.append(mk)
+        counts += mk
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts.ravel(), out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    if nnz >= 2**31:
+        raise ValueError("nnz exceeds int32 range")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    cursor = row_ptr[:-1].copy()
+    rows = np.arange(n, dtype=np.int64)
+    del kk, jj, ii
+    for m, mk in zip(order, masks):
+        dx, dy, dz = offsets[m]
+        flat = mk.ravel()
+        pos = cursor[flat]
+        r = rows[flat]
+        col[pos] = (r + dx + nx * dy + nx * ny * dz).astype(np.int32)
+        v = values[m]
+        if np.isscalar(v):
+            val[pos] = float(v)
+        else:
+            val[pos] = np.asarray(v, dtype=np.float64).ravel()[flat]
+        cursor[flat] += 1
+        del pos, r, flat
+    return CSR(n=n, row_ptr=row_ptr.astype(np.int32), col=col, val=val, grid=(nx, ny, nz))
+
+
+def poisson2d_5pt(nx: int, ny: int) -> CSR:
+    """2D 5-point Laplacian, diagonal 4, neighbours -1, on an nx*ny interior grid."""
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0)]
+    vals = [4.0, -1.0, -1.0, -1.0, -1.0]
+    return stencil_csr((nx, ny, 1), offs, vals)
+
+
+def poisson3d_7pt(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
+    """3D 7-point Laplacian, diagonal 6, neighbours -1."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    vals = [6.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0]
+    return stencil_csr((nx, ny, nz), offs, vals)
+
+
+def q1_27pt(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
+    """3D trilinear (Q1) finite-element Laplacian on a uniform hexahedral mesh.
+
+    Stencil (mesh-size factor dropped): centre 8/3, the 6 face neighbours 0
+    (stored explicitly, they belong to the 27-point pattern), the 12 edge
+    neighbours -1/6, the 8 corner neighbours -1/12.  Values are taken from
+    exact rationals and rounded once to float64.
+    """
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    offs, vals = [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                d = abs(dx) + abs(dy) + abs(dz)
+                v = {0: Fraction(8, 3), 1: Fraction(0), 2: Fraction(-1, 6), 3: Fraction(-1, 12)}[d]
+                offs.append((dx, dy, dz))
+                vals.append(float(v))
+    return stencil_csr((nx, ny, nz), offs, vals)
+
+
+def fv_diffusion(kappa: np.ndarray) -> CSR:
+    """7-point cell-centred finite-volume discretisation of -div(kappa grad u).
+
+    ``kappa`` has shape (nz, ny, nx).  Interior face transmissibility is the
+    harmonic mean 2*k_i*k_j/(k_i+k_j); a boundary face (homogeneous Dirichlet
+    at the face, half a cell away) contributes 2*k_i to the diagonal.  Unit
+    mesh size.  The diagonal is the sum of the row's six face
+    transmissibilities, so the matrix is SPD.
+    """
+    kappa = np.asarray(kappa, dtype=np.float64)
+    nz, ny, nx = kappa.shape
+    def harm(a, b):
+        return 2.0 * a * b / (a + b)
+    diag = np.zeros_like(kappa)
+    off = {}
+    for axis, (dx, dy, dz) in zip((2, 1, 0), ((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+        # transmissibility between cell c and c+e along this axis
+        sl_lo = [slice(None)] * 3
+        sl_hi = [slice(None)] * 3
+        sl_lo[axis] = slice(0, -1)
+        sl_hi[axis] = slice(1, None)
+        t = harm(kappa[tuple(sl_lo)], kappa[tuple(sl_hi)])
+        plus = np.zeros_like(kappa)
+        minus = np.zeros_like(kappa)
+        plus[tuple(sl_lo)] = t   # row c, neighbour c+e
+        minus[tuple(sl_hi)] = t  # row c+e, neighbour c
+        off[(dx, dy, dz)] = -plus
+        off[(-dx, -dy, -dz)] = -minus
+        # diagonal: interior faces plus Dirichlet boundary faces
+        bnd = np.zeros_like(kappa)
+        first = [slice(None)] * 3
+        last = [slice(None)] * 3
+        first[axis] = 0
+        last[axis] = -1
+        bnd[tuple(first)] += 2.0 * kappa[tuple(first)]
+        bnd[tuple(last)] += 2.0 * kappa[tuple(last)]
+        diag += plus + minus + bnd
+    offs = [(0, 0, 0)] + list(off.keys())
+    vals = [diag] + [off[o] for o in off]
+    return stencil_csr((nx, ny, nz), offs, vals)
+
+
+def gaussian_random_field(shape, ell: float, seed: int) -> np.ndarray:
+    """Stationary Gaussian random field on a periodic box, squared-exponential covariance.
+
+    g = real(IFFT(sqrt(S(k)) * FFT(w))) with w i.i.d. N(0,1) from
+    ``numpy.random.default_rng(seed)`` and S(k) = exp(-ell^2 |k|^2 / 2) the
+    (unnormalised) spectral density of exp(-r^2 / (2 ell^2)).  The result is
+    standardised to zero sample mean and unit sample standard deviation.
+    ``shape`` is (nz, ny, nx); ``ell`` is in cells.
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape)
+    nz, ny, nx = shape
+    kz = 2 * np.pi * np.fft.fftfreq(nz)
+    ky = 2 * np.pi * np.fft.fftfreq(ny)
+    kx = 2 * np.pi * np.fft.rfftfreq(nx)
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    amp = np.exp(-0.25 * ell * ell * k2)  # sqrt(S)
+    g = np.fft.irfftn(np.fft.rfftn(w) * amp, s=shape, axes=(0, 1, 2))
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def rhs_uniform(n: int, seed: int) -> np.ndarray:
+    """b ~ U(-1, 1)^n in float64 from ``numpy.random.default_rng(seed)``."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+
+
+def stack_block_diagonal(mats) -> CSR:
+    """Stack equally shaped grid problems along z into one block-diagonal matrix."""
+    mats = list(mats)
+    g = mats[0].grid
+    n0 = mats[0].n
+    for m in mats:
+        if m.grid != g or m.n != n0:
+            raise ValueError("all blocks must share one grid")
+    nnzs = [m.nnz for m in mats]
+    row_ptr = np.zeros(n0 * len(mats) + 1, dtype=np.int64)
+    col = np.empty(sum(nnzs), dtype=np.int32)
+    val = np.empty(sum(nnzs), dtype=np.float64)
+    off = 0
+    for b, m in enumerate(mats):
+        row_ptr[b * n0 + 1:(b + 1) * n0 + 1] = m.row_ptr[1:].astype(np.int64) + off
+        col[off:off + m.nnz] = m.col + b * n0
+        val[off:off + m.nnz] = m.val
+        off += m.nnz
+    return CSR(n=n0 * len(mats), row_ptr=row_ptr.astype(np.int32), col=col, val=val,
+               grid=(g[0], g[1], g[2] * len(mats)), nbatch=len(mats))
+
+
+def config_problem(cfg: int, size: int | None = None):
+    """Matrix and right-hand side of workload ``cfg`` (1..5), optionally at a smaller edge.
+
+    1: 2D 5-point Poisson, 64x64 interior.
+    2: 3D 7-point Poisson, 128^3.
+    3: 3D FV diffusion, kappa = exp(g), g a GRF with correlation length 8 cells, sigma = 1, 256^3.
+    4: 32 stacked 3D FV diffusion problems at 64^3, sigma cycling over (0.5, 1, 2).
+    5: 3D 27-point Q1 Laplacian, 320^3.
+    Returns (CSR, b, meta dict).
+    """
+    if cfg == 1:
+        s = 64 if size is None else size
+        A = poisson2d_5pt(s, s)
+        meta = {"dim": 2}
+    elif cfg == 2:
+        s = 128 if size is None else size
+        A = poisson3d_7pt(s)
+        meta = {"dim": 3}
+    elif cfg == 3:
+        s = 256 if size is None else size
+        g = gaussian_random_field((s, s, s), 8.0, SEED_GRF + 0)
+        A = fv_diffusion(np.exp(1.0 * g))
+        meta = {"dim": 3, "sigma": 1.0}
+    elif cfg == 4:
+        s = 64 if size is None else size
+        sig = (0.5, 1.0, 2.0)
+        probs = []
+        sigmas = []
+        for p in range(32):
+            g = gaussian_random_field((s, s, s), 8.0, SEED_GRF + p)
+            probs.append(fv_diffusion(np.exp(sig[p % 3] * g)))
+            sigmas.append(sig[p % 3])
+        A = stack_block_diagonal(probs)
+        meta = {"dim": 3, "sigmas": sigmas}
+    elif cfg == 5:
+        s = 320 if size is None else size
+        A = q1_27pt(s)
+        meta = {"dim": 3}
+    else:
+        raise ValueError(cfg)
+    b = rhs_uniform(A.n, SEED_RHS + cfg)
+    return A, b, meta
