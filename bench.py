@@ -1,0 +1,227 @@
+"""Benchmark: AMG-PCG on the 3D 7-point Poisson problem at 128^3 (one MI355X).
+
+A step is one complete solve A x = b to ||r|| <= 1e-8 ||b|| from x = 0 with
+the V-cycle preconditioner (box-aggregation hierarchy 128^3 -> 16^3, dense
+coarsest solve) smoothed by the optimal 4th-kind polynomial of degree 4, on
+a hierarchy already resident in HBM (setup excluded, reported separately).
+
+value       = algorithmic HBM bytes of the whole solve / its wall time (GB/s),
+              bytes summed from the per-kernel models below over the launches
+              one solve makes;
+roofline    = the fused recurrence-step kernel on the fine level, its
+              algorithmic bytes per launch / its average duration, timed here
+              with events on the launch stream (difference of degree-6 and
+              degree-2 smoother applications = 4 fused steps);
+cpu_baseline= the FP64 CPU oracle solving the same system once (host cores);
+variants    = time to 1e-8 of the other smoother kinds, of the FP32 hierarchy
+              inside FP64 CG, and (when a trained network is available) of the
+              learned beta, against the plain FP64 optimal 4th kind.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Smoother HBM GB/s (% peak); AMG-PCG time to 1e-8 residual, learned/FP32 vs plain"
+PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
+
+
+# ---- algorithmic byte models (float64 values, int32 indices) ----
+def b_fused(nnz, n, store=True, w=8):
+    # A (w + 4 per entry), gathered direction once, minv, r in, x read+write; + r out, g out
+    return (w + 4) * nnz + (w * 7 if store else w * 5) * n
+
+
+def b_first_zero(n, store, mode, w=8):
+    return w * (2 + 1 + (1 if store else 0) + (1 if (store and mode == 1) else 0)) * n
+
+
+def b_first_res(nnz, n, w=8):
+    return (w + 4) * nnz + 5 * w * n
+
+
+def b_restrict(nnz, n, w=8):
+    return (w + 4) * nnz + 2 * w * n + 4 * n + w * n // 8
+
+
+def b_prolong(n, w=8):
+    return 2 * w * n + 4 * n + w * n // 8
+
+
+def vcycle_bytes(levels, ncp, nbatch, kind, k, w=8):
+    """Algorithmic bytes of one V-cycle (pre from zero, restrict, coarse, prolong, post)."""
+    tot = 0
+    mode = 1 if kind == 3 else 0
+    for (n, nnz) in levels[:-1]:
+        # pre-smoothing from zero
+        tot += b_first_zero(n, k > 1, mode, w) + max(k - 2, 0) * b_fused(nnz, n, True, w) + \
+            (b_fused(nnz, n, False, w) if k > 1 else 0)
+        tot += b_restrict(nnz, n, w) + b_prolong(n, w)
+        # post-smoothing from x
+        tot += b_first_res(nnz, n, w) + max(k - 2, 0) * b_fused(nnz, n, True, w) + \
+            (b_fused(nnz, n, False, w) if k > 1 else 2 * w * n + w * n)
+    nL = levels[-1][0]
+    tot += nbatch * ncp * ncp * 8 + 2 * 8 * nbatch * ncp + 2 * w * nL
+    return tot
+
+
+def pcg_bytes(levels, ncp, nbatch, kind, k, iters, w=8):
+    n, nnz = levels[0]
+    per_it = (12 * nnz + 16 * n) + 48 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 24 * n
+    if w == 4:
+        per_it += 12 * n  # casts r -> f32, z -> f64
+    setup = 16 * n + 16 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 16 * n
+    return setup + iters * per_it
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--kind", type=int, default=2)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2407_09848_amd as amg
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    A, b, _ = W.config_problem(2, size=args.size)
+    rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    L = amg.amg_num_levels(h)
+    levels = [amg.amg_level_info(h, l) for l in range(L)]
+    nL = levels[-1][0]
+    ncp = (nL + 63) // 64 * 64
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+
+    def solve(handle, kind, k):
+        return amg.pcg_solve(handle, kind, k, bd, x, True, 1e-8, 1000)
+
+    for _ in range(args.warmup):
+        solve(h, args.kind, args.degree)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    iters = []
+    for _ in range(args.steps):
+        rc, it, rel, _ = solve(h, args.kind, args.degree)
+        iters.append(it)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    it = iters[-1]
+    solve_bytes = pcg_bytes(levels, ncp, 1, args.kind, args.degree, it)
+    value = solve_bytes / (ms * 1e-3) / 1e9
+
+    # ---- fused recurrence step on the fine level: events around smoother applications ----
+    n0, nnz0 = levels[0]
+    xs = torch.zeros(n0, dtype=torch.float64, device="cuda")
+    reps = 50
+
+    def time_apply(k):
+        for _ in range(3):
+            amg.smoother_apply(h, 0, args.kind, k, bd, xs, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            amg.smoother_apply(h, 0, args.kind, k, bd, xs, True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t6, t2 = time_apply(6), time_apply(2)
+    t_fused_ms = (t6 - t2) / 4.0
+    fused_bytes = b_fused(nnz0, n0, True)
+    achieved = fused_bytes / (t_fused_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
+                "kernel": "k_fused<double,0,true> (fine level, 128^3)",
+                "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2)}
+
+    # ---- variants: other kinds, FP32 hierarchy ----
+    variants = {}
+    if not args.no_variants:
+        def time_solve(handle, kind, k, reps=3):
+            solve(handle, kind, k)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                rc, itv, relv, _ = solve(handle, kind, k)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps, itv
+        names = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
+        for kind in (0, 1, 2, 3):
+            tm, itv = time_solve(h, kind, args.degree)
+            variants[f"fp64_{names[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv}
+        h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
+        tm, itv = time_solve(h32, args.kind, args.degree)
+        xr = x.cpu().numpy()
+        variants[f"fp32_{names[args.kind]}_k{args.degree}"] = {
+            "ms": round(tm, 3), "iters": itv,
+            "true_relres": float(np.linalg.norm(b - A.to_scipy() @ xr) / np.linalg.norm(b))}
+        amg.amg_destroy(h32)
+        base = variants[f"fp64_{names[args.kind]}_k{args.degree}"]["ms"]
+        for v in variants.values():
+            v["vs_plain_fp64"] = round(v["ms"] / base, 3)
+    amg.amg_destroy(h)
+
+    # ---- CPU baseline: the oracle solving the same system once ----
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import amg as OA
+        with threadpool_limits(limits=1):
+            As = A.to_scipy()
+            H = OA.build_hierarchy(As, A.grid)
+            t0 = time.perf_counter()
+            res, _ = OA.amg_pcg(As, b, A.grid, args.kind, args.degree, H=H)
+            cpu_s = time.perf_counter() - t0
+        cpu_bytes = pcg_bytes(levels, ncp, 1, args.kind, args.degree, res.iters)
+        cpu = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full FP64 oracle AMG-PCG solve of the same {args.size}^3 system "
+                         f"({res.iters} iterations, {cpu_s:.1f} s, scipy/numpy single thread)",
+               "solve_s": round(cpu_s, 2), "iters": res.iters}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"poisson3d_7pt_{args.size}^3_amg_pcg_to_1e-8",
+                   "smoother": {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}[args.kind],
+                   "degree": args.degree, "n": int(n0), "nnz": int(nnz0), "levels": [int(l[0]) for l in levels],
+                   "iters": it, "setup_s": round(setup_s, 3)},
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

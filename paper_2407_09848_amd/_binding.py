@@ -1,0 +1,231 @@
+"""ctypes binding of libamgpoly.so.  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libamgpoly.so")
+
+AMG_OK, AMG_NOT_CONVERGED = 0, 1
+AMG_EINVAL, AMG_ENOTSPD, AMG_ENOMEM, AMG_EHIP, AMG_EBREAKDOWN, AMG_ENAN, AMG_ECAPACITY = -1, -2, -3, -4, -5, -6, -7
+AMG_L1JAC, AMG_CHEB4, AMG_OPTCHEB4, AMG_OPTCHEB1 = 0, 1, 2, 3
+AMG_FP64, AMG_FP32 = 0, 1
+AMG_MAX_DEGREE = 12
+
+__all__ = [
+    "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info",
+    "amg_level_export", "amg_default_beta", "amg_default_astar", "amg_set_beta", "amg_reset_beta",
+    "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
+    "vcycle_apply", "pcg_solve", "amg_strerror",
+    "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
+    "AMG_EBREAKDOWN", "AMG_ENAN", "AMG_ECAPACITY", "AMG_L1JAC", "AMG_CHEB4", "AMG_OPTCHEB4",
+    "AMG_OPTCHEB1", "AMG_FP64", "AMG_FP32", "AMG_MAX_DEGREE",
+]
+
+
+class AmgOpts(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("nbatch", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class AmgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {amg_strerror(code)} ({code})")
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+_SIGS = {
+    "amg_setup": (_I, [_I64, _I64, _P, _P, _P, ctypes.POINTER(AmgOpts), _P, ctypes.POINTER(_P)]),
+    "amg_destroy": (_I, [_P]),
+    "amg_num_levels": (_I, [_P, ctypes.POINTER(_I)]),
+    "amg_level_info": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "amg_level_export": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "amg_default_beta": (_I, [_I, ctypes.POINTER(_D)]),
+    "amg_default_astar": (_I, [_I, ctypes.POINTER(_D)]),
+    "amg_set_beta": (_I, [_P, _I, _I, ctypes.POINTER(_D)]),
+    "amg_reset_beta": (_I, [_P]),
+    "amg_spmv": (_I, [_P, _I, _P, _P, _P]),
+    "smoother_apply": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
+    "amg_restrict_residual": (_I, [_P, _I, _P, _P, _P, _P]),
+    "amg_prolong_add": (_I, [_P, _I, _P, _P, _P]),
+    "amg_coarse_solve": (_I, [_P, _P, _P, _P]),
+    "vcycle_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "pcg_solve": (_I, [_P, _I, _I, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
+                       ctypes.POINTER(_D), _P]),
+    "amg_strerror": (ctypes.c_char_p, [_I]),
+}
+
+
+def lib():
+    """Load libamgpoly.so (raises ImportError if it is not built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2407_09848_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, n=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc, where, allow=(AMG_OK,)):
+    if rc not in allow:
+        raise AmgError(rc, where)
+    return rc
+
+
+def amg_strerror(code: int) -> str:
+    return lib().amg_strerror(code).decode()
+
+
+def amg_setup(row_ptr, col, val, nx, ny, nz, nbatch=1, max_coarse=4096, precision=AMG_FP64):
+    """Build the hierarchy for the device CSR matrix (int32 row_ptr/col, float64 val); returns the handle."""
+    import torch
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    o = AmgOpts(nx, ny, nz, nbatch, max_coarse, precision)
+    h = ctypes.c_void_p()
+    rc = lib().amg_setup(n, nnz, _ptr(row_ptr, torch.int32, name="row_ptr"), _ptr(col, torch.int32, name="col"),
+                         _ptr(val, torch.float64, nnz, "val"), ctypes.byref(o), _stream(), ctypes.byref(h))
+    _check(rc, "amg_setup")
+    return h
+
+
+def amg_destroy(h):
+    return lib().amg_destroy(h)
+
+
+def amg_num_levels(h) -> int:
+    v = _I()
+    _check(lib().amg_num_levels(h, ctypes.byref(v)), "amg_num_levels")
+    return v.value
+
+
+def amg_level_info(h, level):
+    n, nnz = _I64(), _I64()
+    _check(lib().amg_level_info(h, level, ctypes.byref(n), ctypes.byref(nnz)), "amg_level_info")
+    return n.value, nnz.value
+
+
+def amg_level_export(h, level):
+    """(row_ptr, col, val, minv) of level l as new device tensors."""
+    import torch
+    n, nnz = amg_level_info(h, level)
+    dev = torch.device("cuda")
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    cl = torch.empty(nnz, dtype=torch.int32, device=dev)
+    vl = torch.empty(nnz, dtype=torch.float64, device=dev)
+    mi = torch.empty(n, dtype=torch.float64, device=dev)
+    _check(lib().amg_level_export(h, level, _ptr(rp), _ptr(cl), _ptr(vl), _ptr(mi), _stream()), "amg_level_export")
+    return rp, cl, vl, mi
+
+
+def amg_default_beta(degree):
+    buf = (_D * max(degree, 1))()
+    _check(lib().amg_default_beta(degree, buf), "amg_default_beta")
+    return [buf[i] for i in range(degree)]
+
+
+def amg_default_astar(degree):
+    v = _D()
+    _check(lib().amg_default_astar(degree, ctypes.byref(v)), "amg_default_astar")
+    return v.value
+
+
+def amg_set_beta(h, degree, level, beta):
+    buf = (_D * len(beta))(*[float(b) for b in beta])
+    if len(beta) != degree:
+        raise ValueError("beta must have `degree` entries")
+    return _check(lib().amg_set_beta(h, degree, level, buf), "amg_set_beta")
+
+
+def amg_reset_beta(h):
+    return _check(lib().amg_reset_beta(h), "amg_reset_beta")
+
+
+def amg_spmv(h, level, x, y):
+    import torch
+    n, _ = amg_level_info(h, level)
+    return _check(lib().amg_spmv(h, level, _ptr(x, torch.float64, n, "x"), _ptr(y, torch.float64, n, "y"),
+                                 _stream()), "amg_spmv")
+
+
+def smoother_apply(h, level, kind, degree, b, x, x_is_zero=False):
+    import torch
+    n, _ = amg_level_info(h, level)
+    return _check(lib().smoother_apply(h, level, kind, degree, _ptr(b, torch.float64, n, "b"),
+                                       _ptr(x, torch.float64, n, "x"), int(bool(x_is_zero)), _stream()),
+                  "smoother_apply")
+
+
+def amg_restrict_residual(h, level, b, x, bc):
+    import torch
+    n, _ = amg_level_info(h, level)
+    nc, _ = amg_level_info(h, level + 1)
+    return _check(lib().amg_restrict_residual(h, level, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"),
+                                              _ptr(bc, torch.float64, nc, "bc"), _stream()), "amg_restrict_residual")
+
+
+def amg_prolong_add(h, level, xc, x):
+    import torch
+    n, _ = amg_level_info(h, level)
+    nc, _ = amg_level_info(h, level + 1)
+    return _check(lib().amg_prolong_add(h, level, _ptr(xc, torch.float64, nc, "xc"), _ptr(x, torch.float64, n, "x"),
+                                        _stream()), "amg_prolong_add")
+
+
+def amg_coarse_solve(h, b, x):
+    import torch
+    L = amg_num_levels(h) - 1
+    n, _ = amg_level_info(h, L)
+    return _check(lib().amg_coarse_solve(h, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"),
+                                         _stream()), "amg_coarse_solve")
+
+
+def vcycle_apply(h, kind, degree, r, z):
+    import torch
+    n, _ = amg_level_info(h, 0)
+    return _check(lib().vcycle_apply(h, kind, degree, _ptr(r, torch.float64, n, "r"), _ptr(z, torch.float64, n, "z"),
+                                     _stream()), "vcycle_apply")
+
+
+def pcg_solve(h, kind, degree, b, x, x_is_zero=True, rtol=1e-8, maxit=1000, flexible=False, history=False):
+    """Returns (rc, iters, relres, hist list or None); rc is AMG_OK or AMG_NOT_CONVERGED (errors raise)."""
+    import torch
+    n, _ = amg_level_info(h, 0)
+    it, rel = _I(), _D()
+    hist = (_D * (maxit + 1))() if history else None
+    rc = lib().pcg_solve(h, kind, degree, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"),
+                         int(bool(x_is_zero)), float(rtol), int(maxit), int(bool(flexible)), ctypes.byref(it),
+                         ctypes.byref(rel), hist, _stream())
+    _check(rc, "pcg_solve", allow=(AMG_OK, AMG_NOT_CONVERGED))
+    return rc, it.value, rel.value, ([hist[i] for i in range(it.value + 1)] if history else None)

@@ -1,0 +1,195 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "amgpoly.h"
+
+namespace amgp {
+
+constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int kSlice = 64;    // sliced-ELL slice height = one wavefront, one row per lane
+constexpr int kBlock = 256;   // threads per block for row-parallel kernels (4 waves)
+constexpr int kMaxChildren = 8;  // 2x2x2 box aggregates
+constexpr int kDenseTile = 64;   // dense coarsest level padded to a multiple of this
+
+// Sliced ELLPACK matrix: rows grouped in slices of 64 (one per lane of a
+// wavefront); inside slice s the entry j of lane l sits at sptr[s] + 64*j + l,
+// so the 64 lanes of a wavefront load consecutive addresses.  Rows shorter
+// than the slice width are padded with (col = row, val = 0).
+template <typename T>
+struct Ell {
+  int64_t n = 0;
+  int64_t nslices = 0;
+  int64_t padded = 0;
+  int32_t* sptr = nullptr;  // [nslices + 1]
+  int32_t* col = nullptr;   // [padded]
+  T* val = nullptr;         // [padded]
+};
+
+template <typename T>
+struct EllView {
+  const int32_t* __restrict__ sptr;
+  const int32_t* __restrict__ col;
+  const T* __restrict__ val;
+};
+
+template <typename T>
+inline EllView<T> view(const Ell<T>& e) {
+  return EllView<T>{e.sptr, e.col, e.val};
+}
+
+// Work vectors of one level in one precision.
+template <typename T>
+struct Vecs {
+  T* b = nullptr;   // right-hand side of this level (levels > 0, or FP32 level 0)
+  T* x = nullptr;   // solution/correction of this level
+  T* r = nullptr;   // smoother recurrence residual
+  T* g0 = nullptr;  // direction ping-pong (z / d), also l1-Jacobi ping-pong
+  T* g1 = nullptr;
+  T* minv = nullptr;
+};
+
+struct Level {
+  int64_t n = 0, nnz = 0;
+  int nx = 1, ny = 1, nz = 1;  // per-problem grid
+  // Galerkin operator in CSR (float64), kept for export and the next Galerkin product.
+  int32_t* csr_ptr = nullptr;
+  int32_t* csr_col = nullptr;
+  double* csr_val = nullptr;
+  Ell<double> A64;
+  Ell<float> A32;
+  Vecs<double> v64;
+  Vecs<float> v32;
+  // transfer to level + 1
+  int64_t nc = 0;                 // rows of level + 1
+  int32_t* agg = nullptr;         // [n] aggregate of each row
+  int32_t* children = nullptr;    // [nc * 8] rows of each aggregate, ascending, -1 padded
+};
+
+struct Handle {
+  int nlevels = 0;
+  int nbatch = 1;
+  int precision = AMG_FP64;
+  int max_coarse = 4096;
+  std::vector<Level> lv;
+  // coarsest level: dense inverse per problem, padded to ncp
+  int64_t ncl = 0;   // rows per problem on the coarsest level
+  int64_t ncp = 0;   // padded
+  double* ainv = nullptr;  // [nbatch][ncp][ncp]
+  double* cb = nullptr;    // [nbatch * ncp] padded coarse rhs
+  double* cx = nullptr;    // [nbatch * ncp] padded coarse solution
+  // beta weights: [level][degree][j]
+  std::vector<double> beta;  // size nlevels * (AMG_MAX_DEGREE+1) * AMG_MAX_DEGREE
+  // reductions and CG workspace (fine level, float64)
+  double* partial = nullptr;  // 2 * maxblocks
+  double* scal = nullptr;     // device scalars
+  double* hscal = nullptr;    // pinned host mirror
+  int* dflag = nullptr;       // device error flags
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_rold = nullptr;
+  double *tmp64 = nullptr;    // level-0 scratch (n0)
+  double& beta_at(int l, int k, int j) {
+    return beta[((size_t)l * (AMG_MAX_DEGREE + 1) + k) * AMG_MAX_DEGREE + j];
+  }
+};
+
+// Device scalar slots in Handle::scal.
+enum Scal { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_AUX, S_NSCAL };
+// Device flag slots in Handle::dflag.
+enum Flag { F_NOTSPD = 0, F_CAPACITY, F_BREAKDOWN, F_NAN, F_BADCSR, F_NFLAG };
+
+// ---- error plumbing ----
+#define AMGP_HIP(call)                          \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return AMG_EHIP;      \
+  } while (0)
+#define AMGP_TRY(call)                          \
+  do {                                          \
+    int rc_ = (call);                           \
+    if (rc_ != AMG_OK) return rc_;              \
+  } while (0)
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- sparse / vector kernel launchers (kernels_sparse.hip) ----
+template <typename T>
+int launch_spmv(hipStream_t s, const Ell<T>& A, const T* x, T* y);
+template <typename T>
+int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r);
+// smoother steps
+template <typename T>
+int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
+                      T* x, double c, double w);
+template <typename T>
+int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
+                     T* g, double c);
+template <typename T>
+int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
+                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev);
+template <typename T>
+int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew);
+template <typename T>
+int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x);
+// transfers
+template <typename T>
+int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
+                    const T* x, T* bc);
+template <typename T>
+int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x);
+// vectors
+template <typename T>
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y);  // y += a x
+template <typename T>
+int launch_copy(hipStream_t s, int64_t n, const T* x, T* y);
+template <typename T>
+int launch_fill(hipStream_t s, int64_t n, T v, T* y);
+template <typename Tin, typename Tout>
+int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y);
+// coarse rhs gather/scatter between level vectors and the padded dense layout
+template <typename T>
+int launch_pad_in(hipStream_t s, int nbatch, int64_t nl, int64_t np, const T* b, double* out);
+template <typename T>
+int launch_pad_out(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* in, T* x);
+// CG (float64)
+int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
+                double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
+int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
+                    unsigned* nblocks);
+int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
+                     double* r, double* rold, double* partial, unsigned* nblocks);
+int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p);
+int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag);
+enum ReduceMode { RED_BB = 0, RED_RZ0, RED_ALPHA, RED_RR, RED_BETA, RED_BETA_FLEX };
+int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag);
+
+// ---- setup kernels (kernels_setup.hip) ----
+// row_ptr monotone from 0 to nnz, columns strictly increasing within a row and in [0, n)
+int validate_csr(hipStream_t s, int64_t n, int64_t nnz, const int32_t* ptr, const int32_t* col, int* flag);
+int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                   double* minv, int* flag);
+int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                Ell<double>* out);
+int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out);
+int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int32_t* agg, int32_t* children,
+                      int* cnx, int* cny, int* cnz);
+int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+             const int32_t* agg, int64_t nc, const int32_t* children, int32_t** cptr, int32_t** ccol,
+             double** cval, int64_t* cnnz, int* flag);
+int launch_to_dense(hipStream_t s, int nbatch, int64_t nl, int64_t np, const int32_t* ptr, const int32_t* col,
+                    const double* val, double* dense, int* flag);
+void free_ell(Ell<double>& e);
+void free_ell(Ell<float>& e);
+
+// ---- dense kernels (kernels_dense.hip) ----
+// In place: dense[nbatch][np][np] (SPD, lower part used) -> inverse A^{-1}, full symmetric.
+int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np, double* dense, int* flag);
+int launch_coarse_gemv(hipStream_t s, int nbatch, int64_t np, const double* ainv, const double* b, double* x);
+
+}  // namespace amgp

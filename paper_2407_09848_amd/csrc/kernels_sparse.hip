@@ -1,0 +1,572 @@
+// Row-parallel sparse and vector kernels for gfx950: SpMV, the fused smoother
+// recurrence steps, grid transfers and the CG vector updates with
+// deterministic two-stage reductions.
+//
+// Layout and launch shape: one row per lane, 256-thread blocks (4 waves), the
+// matrix in sliced ELL with 64-row slices so that every load of val/col by a
+// wavefront is one contiguous 512 B (float64) segment.  Blocks are remapped so
+// that each of the 8 XCDs (which receive workgroups round-robin) walks one
+// contiguous range of rows: the neighbours gathered by a row (the previous
+// and next grid lines and planes) were then recently touched by the same
+// XCD and are served from its L2 instead of HBM.
+#include "internal.h"
+
+namespace amgp {
+
+namespace {
+
+constexpr int kXcd = 8;
+
+inline unsigned xcd_grid(int64_t n) {
+  unsigned g = grid_for(n);
+  return (g + kXcd - 1) / kXcd * kXcd;
+}
+
+// Logical block index: block b runs on XCD b % 8; give XCD x the contiguous
+// blocks [x * G/8, (x+1) * G/8).  G is a multiple of 8 (xcd_grid).
+__device__ __forceinline__ int64_t logical_block() {
+  const unsigned per = gridDim.x / kXcd;
+  return (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
+
+__device__ __forceinline__ int64_t row_index() { return logical_block() * kBlock + threadIdx.x; }
+
+template <typename T>
+__device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restrict__ x) {
+  // every lane of the wavefront is in the same slice: read its bounds once, as scalars
+  const int s = __builtin_amdgcn_readfirstlane((int)(row >> 6));
+  const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
+  const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
+  const int lane = (int)(row & 63);
+  T acc = T(0);
+#pragma unroll 4
+  for (int p = beg + lane; p < end; p += kSlice) {
+    acc += A.val[p] * x[A.col[p]];
+  }
+  return acc;
+}
+
+// Wave-level sum with cross-lane shuffles, then across the block's 4 waves via LDS.
+// Fixed association order: bitwise reproducible for a fixed launch shape.
+__device__ __forceinline__ double block_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  __shared__ double part[kBlock / kWave];
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & 63) == 0) part[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kBlock / kWave; ++i) s += part[i];
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// SpMV and residual
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, EllView<T> A, const T* __restrict__ x,
+                                                 T* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = ell_dot(A, i, x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ r) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  r[i] = b[i] - ell_dot(A, i, x);
+}
+
+// ---------------------------------------------------------------------------
+// Smoother recurrence steps.
+//
+// MODE 0 (4th kind, optimal 4th kind; eqs. polsmoother / polsmootheropt):
+//   r   = r_in - A g_old                      (residual of the previous step)
+//   g   = alpha g_old + c M^{-1} r            (z^(j))
+//   x  += wprev g_old + w g                   (beta_j-weighted update)
+// MODE 1 (1st kind; Algorithm 1, the loop body):
+//   r   = r_in - M^{-1} A g_old               (r^(j) = r^(j-1) - s^(j))
+//   g   = alpha g_old + c r                   (d^(j) = rho_j rho_{j-1} d + (2 rho_j / delta) r)
+//   x  += wprev g_old + g
+// g_old is gathered by neighbouring rows, so g is written to the other buffer
+// of a ping-pong pair; r and x are row-local and updated in place.  wprev
+// carries an x update deferred by a first step that gathered x itself.
+// STORE = false on the last step of an application: only x is needed.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                  const T* __restrict__ gold, T* __restrict__ gnew,
+                                                  const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
+                                                  T wprev) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const T ag = ell_dot(A, i, gold);
+  const T mi = minv[i];
+  const T go = gold[i];
+  const T r = (MODE == 0) ? rin[i] - ag : rin[i] - mi * ag;
+  const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
+  x[i] = x[i] + wprev * go + w * g;
+  if (STORE) {
+    rout[i] = r;
+    gnew[i] = g;
+  }
+}
+
+// First step from x = 0 (r^(0) = b, no SpMV).
+// MODE 0: g = c M^{-1} b, x = w g.   MODE 1: r = M^{-1} b, g = r / c (c = theta), x = g.
+template <typename T, int MODE, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __restrict__ minv,
+                                                       const T* __restrict__ b, T* __restrict__ g,
+                                                       T* __restrict__ r, T* __restrict__ x, T c, T w) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const T mi = minv[i];
+  if (MODE == 0) {
+    const T gi = c * (mi * b[i]);
+    x[i] = w * gi;
+    if (STORE) g[i] = gi;
+  } else {
+    const T ri = mi * b[i];
+    const T gi = ri / c;
+    x[i] = gi;
+    if (STORE) {
+      r[i] = ri;
+      g[i] = gi;
+    }
+  }
+}
+
+// First step from a nonzero x: r^(0) from b - A x.  x is gathered here, so its
+// update is deferred to the next step (or a separate axpy when k = 1).
+// MODE 0: r = b - A x, g = c M^{-1} r.   MODE 1: r = M^{-1}(b - A x), g = r / c (c = theta).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                      const T* __restrict__ b, const T* __restrict__ x,
+                                                      T* __restrict__ r, T* __restrict__ g, T c) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const T res = b[i] - ell_dot(A, i, x);
+  const T mi = minv[i];
+  if (MODE == 0) {
+    r[i] = res;
+    g[i] = c * (mi * res);
+  } else {
+    const T ri = mi * res;
+    r[i] = ri;
+    g[i] = ri / c;
+  }
+}
+
+// One l1-Jacobi sweep x_new = x_old + M^{-1}(b - A x_old) (eq. l1smooth).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                   const T* __restrict__ b, const T* __restrict__ xold,
+                                                   T* __restrict__ xnew) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  xnew[i] = xold[i] + minv[i] * (b[i] - ell_dot(A, i, xold));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_zero(int64_t n, const T* __restrict__ minv,
+                                                        const T* __restrict__ b, T* __restrict__ x) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  x[i] = minv[i] * b[i];
+}
+
+// ---------------------------------------------------------------------------
+// Grid transfers (piecewise-constant P from box aggregates)
+// ---------------------------------------------------------------------------
+// b_c[I] = sum over the rows i of aggregate I (ascending) of (b_i - (A x)_i).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, EllView<T> A, const int32_t* __restrict__ ch,
+                                                     const T* __restrict__ b, const T* __restrict__ x,
+                                                     T* __restrict__ bc) {
+  const int64_t I = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (I >= nc) return;
+  T s = T(0);
+  for (int c = 0; c < kMaxChildren; ++c) {
+    const int i = ch[I * kMaxChildren + c];
+    if (i < 0) break;
+    // scalar-slice trick does not apply here (children of one wave span slices)
+    const int sl = i >> 6, lane = i & 63;
+    const int beg = A.sptr[sl], end = A.sptr[sl + 1];
+    T acc = T(0);
+    for (int p = beg + lane; p < end; p += kSlice) acc += A.val[p] * x[A.col[p]];
+    s += b[i] - acc;
+  }
+  bc[I] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t* __restrict__ agg,
+                                                    const T* __restrict__ xc, T* __restrict__ x) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  x[i] = x[i] + xc[agg[i]];
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = y[i] + a * x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T v, T* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restrict__ x, Tout* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = (Tout)x[i];
+}
+
+// level vector (nbatch blocks of nl) <-> padded dense layout (nbatch blocks of np >= nl, pad = 0)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pad_in(int64_t total, int64_t nl, int64_t np, const T* __restrict__ b,
+                                                   double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const int64_t p = i / np, j = i % np;
+  out[i] = j < nl ? (double)b[p * nl + j] : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pad_out(int64_t total, int64_t nl, int64_t np,
+                                                    const double* __restrict__ in, T* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const int64_t p = i / nl, j = i % nl;
+  x[i] = (T)in[p * np + j];
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels (float64): fused SpMV + dot, update + dot, and a single-block
+// second-stage reduction that also forms the CG scalars on the device.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __restrict__ a,
+                                                 const double* __restrict__ b, const double* __restrict__ c,
+                                                 const double* __restrict__ d, double* __restrict__ partial) {
+  const int64_t i = row_index();
+  double v = 0.0, u = 0.0;
+  if (i < n) {
+    v = a[i] * b[i];
+    if (c) u = c[i] * d[i];
+  }
+  const double sv = block_sum(v);
+  __syncthreads();
+  const double su = c ? block_sum(u) : 0.0;
+  if (threadIdx.x == 0) {
+    partial[logical_block()] = sv;
+    partial[gridDim.x + logical_block()] = su;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> A, const double* __restrict__ p,
+                                                     double* __restrict__ q, double* __restrict__ partial) {
+  const int64_t i = row_index();
+  double v = 0.0;
+  if (i < n) {
+    const double qi = ell_dot(A, i, p);
+    q[i] = qi;
+    v = p[i] * qi;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) partial[logical_block()] = s;
+}
+
+// x += alpha p, r -= alpha q (alpha from the device scalars), partial (r, r);
+// rold (flexible CG) receives the previous r.
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ scal,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      double* __restrict__ rold, double* __restrict__ partial) {
+  const int64_t i = row_index();
+  const double alpha = scal[S_ALPHA];
+  double v = 0.0;
+  if (i < n) {
+    x[i] = x[i] + alpha * p[i];
+    const double ro = r[i];
+    if (rold) rold[i] = ro;
+    const double rn = ro - alpha * q[i];
+    r[i] = rn;
+    v = rn * rn;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) partial[logical_block()] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double* __restrict__ scal,
+                                                       const double* __restrict__ z, double* __restrict__ p) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  p[i] = z[i] + scal[S_BETA] * p[i];
+}
+
+__global__ __launch_bounds__(1024) void k_reduce(int mode, unsigned nb, const double* __restrict__ partial,
+                                                 double* __restrict__ scal, int* __restrict__ flag) {
+  __shared__ double sm[2][1024 / kWave];
+  double v = 0.0, u = 0.0;
+  for (unsigned j = threadIdx.x; j < nb; j += 1024) {
+    v += partial[j];
+    u += partial[nb + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    v += __shfl_xor(v, off, kWave);
+    u += __shfl_xor(u, off, kWave);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][threadIdx.x / kWave] = v;
+    sm[1][threadIdx.x / kWave] = u;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double s = 0.0, t = 0.0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    s += sm[0][w];
+    t += sm[1][w];
+  }
+  switch (mode) {
+    case RED_BB:
+      scal[S_BB] = s;
+      break;
+    case RED_RZ0:
+      scal[S_RZ] = s;
+      break;
+    case RED_ALPHA:
+      scal[S_PQ] = s;
+      if (!(s > 0.0)) flag[F_BREAKDOWN] = 1;
+      scal[S_ALPHA] = scal[S_RZ] / s;
+      break;
+    case RED_RR:
+      scal[S_RR] = s;
+      if (!(s == s) || s > 1.0e300) flag[F_NAN] = 1;
+      break;
+    case RED_BETA:
+      scal[S_BETA] = s / scal[S_RZ];
+      scal[S_RZ] = s;
+      break;
+    case RED_BETA_FLEX:  // s = (r_new, z_new), t = (r_old, z_new)
+      scal[S_BETA] = (s - t) / scal[S_RZ];
+      scal[S_RZ] = s;
+      break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finite(int64_t n, const double* __restrict__ x,
+                                                         int* __restrict__ flag) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const double v = x[i];
+  if (!(v == v) || v > 1.0e308 || v < -1.0e308) flag[F_NAN] = 1;
+}
+
+}  // namespace
+
+#define LAUNCH_OK() (hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP)
+
+template <typename T>
+int launch_spmv(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
+  hipLaunchKernelGGL(k_spmv<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r) {
+  hipLaunchKernelGGL(k_residual<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
+                      T* x, double c, double w) {
+  dim3 gr(xcd_grid(n)), bl(kBlock);
+  if (mode == 0 && store)
+    hipLaunchKernelGGL((k_first_zero<T, 0, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_first_zero<T, 0, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+  else if (store)
+    hipLaunchKernelGGL((k_first_zero<T, 1, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+  else
+    hipLaunchKernelGGL((k_first_zero<T, 1, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
+                     T* g, double c) {
+  dim3 gr(xcd_grid(A.n)), bl(kBlock);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_first_res<T, 0>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+  else
+    hipLaunchKernelGGL((k_first_res<T, 1>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
+                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev) {
+  dim3 gr(xcd_grid(A.n)), bl(kBlock);
+  const T a_ = (T)alpha, c_ = (T)c, w_ = (T)w, wp_ = (T)wprev;
+  if (mode == 0 && store)
+    hipLaunchKernelGGL((k_fused<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_fused<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
+                       c_, w_, wp_);
+  else if (store)
+    hipLaunchKernelGGL((k_fused<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_);
+  else
+    hipLaunchKernelGGL((k_fused<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
+                       c_, w_, wp_);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew) {
+  hipLaunchKernelGGL(k_jacobi<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), minv, b, xold, xnew);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x) {
+  hipLaunchKernelGGL(k_jacobi_zero<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, minv, b, x);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
+                    const T* x, T* bc) {
+  hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, view(A), children, b, x, bc);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x) {
+  hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, agg, xc, x);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y) {
+  hipLaunchKernelGGL(k_axpy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, (T)a, x, y);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_copy(hipStream_t s, int64_t n, const T* x, T* y) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, x, y);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_fill(hipStream_t s, int64_t n, T v, T* y) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, v, y);
+  return LAUNCH_OK();
+}
+
+template <typename Tin, typename Tout>
+int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y) {
+  hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, x, y);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_pad_in(hipStream_t s, int nbatch, int64_t nl, int64_t np, const T* b, double* out) {
+  const int64_t total = (int64_t)nbatch * np;
+  hipLaunchKernelGGL(k_pad_in<T>, dim3(grid_for(total)), dim3(kBlock), 0, s, total, nl, np, b, out);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_pad_out(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* in, T* x) {
+  const int64_t total = (int64_t)nbatch * nl;
+  hipLaunchKernelGGL(k_pad_out<T>, dim3(grid_for(total)), dim3(kBlock), 0, s, total, nl, np, in, x);
+  return LAUNCH_OK();
+}
+
+int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
+                double* partial, unsigned* nblocks) {
+  const unsigned g = xcd_grid(n);
+  hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
+  *nblocks = g;
+  return LAUNCH_OK();
+}
+
+int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
+                    unsigned* nblocks) {
+  const unsigned g = xcd_grid(A.n);
+  hipLaunchKernelGGL(k_spmv_dot, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
+  *nblocks = g;
+  return LAUNCH_OK();
+}
+
+int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
+                     double* r, double* rold, double* partial, unsigned* nblocks) {
+  const unsigned g = xcd_grid(n);
+  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
+  *nblocks = g;
+  return LAUNCH_OK();
+}
+
+int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p) {
+  hipLaunchKernelGGL(k_cg_pupdate, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, scal, z, p);
+  return LAUNCH_OK();
+}
+
+int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, mode, nblocks, partial, scal, flag);
+  return LAUNCH_OK();
+}
+
+int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
+  hipLaunchKernelGGL(k_check_finite, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, x, flag);
+  return LAUNCH_OK();
+}
+
+#define INST(T)                                                                                               \
+  template int launch_spmv<T>(hipStream_t, const Ell<T>&, const T*, T*);                                      \
+  template int launch_residual<T>(hipStream_t, const Ell<T>&, const T*, const T*, T*);                        \
+  template int launch_first_zero<T>(hipStream_t, int, bool, int64_t, const T*, const T*, T*, T*, T*, double,   \
+                                    double);                                                                  \
+  template int launch_first_res<T>(hipStream_t, int, const Ell<T>&, const T*, const T*, const T*, T*, T*,      \
+                                   double);                                                                   \
+  template int launch_fused<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, const T*, T*, T*,  \
+                               double, double, double, double);                                               \
+  template int launch_jacobi<T>(hipStream_t, const Ell<T>&, const T*, const T*, const T*, T*);                \
+  template int launch_jacobi_zero<T>(hipStream_t, int64_t, const T*, const T*, T*);                           \
+  template int launch_restrict<T>(hipStream_t, const Ell<T>&, int64_t, const int32_t*, const T*, const T*, T*); \
+  template int launch_prolong<T>(hipStream_t, int64_t, const int32_t*, const T*, T*);                         \
+  template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*);                                    \
+  template int launch_copy<T>(hipStream_t, int64_t, const T*, T*);                                           \
+  template int launch_fill<T>(hipStream_t, int64_t, T, T*);                                                   \
+  template int launch_pad_in<T>(hipStream_t, int, int64_t, int64_t, const T*, double*);                       \
+  template int launch_pad_out<T>(hipStream_t, int, int64_t, int64_t, const double*, T*);
+
+INST(double)
+INST(float)
+template int launch_cast<double, float>(hipStream_t, int64_t, const double*, float*);
+template int launch_cast<float, double>(hipStream_t, int64_t, const float*, double*);
+
+}  // namespace amgp

@@ -1,0 +1,62 @@
+"""Helpers shared by the GPU tests: move workload matrices to the device and
+build hierarchies through the C ABI.  (Not collected: no test functions.)"""
+import contextlib
+
+import numpy as np
+
+KINDS = [0, 1, 2, 3]
+
+
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a, dtype=None):
+    torch = torch_cuda()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda", dtype=dtype) if dtype is not None else t.to("cuda")
+
+
+def host(t):
+    return t.detach().to("cpu").numpy()
+
+
+def nan_vec(n):
+    torch = torch_cuda()
+    return torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+
+
+@contextlib.contextmanager
+def hierarchy(A, nbatch=1, max_coarse=4096, precision=0):
+    import paper_2407_09848_amd as amg
+    torch = torch_cuda()
+    nx, ny, nz = A.grid
+    nz_per = nz // nbatch
+    rp = dev(A.row_ptr.astype(np.int32))
+    cl = dev(A.col.astype(np.int32))
+    vl = dev(A.val.astype(np.float64))
+    h = amg.amg_setup(rp, cl, vl, nx, ny, nz_per, nbatch, max_coarse, precision)
+    torch.cuda.synchronize()
+    try:
+        yield h
+    finally:
+        torch.cuda.synchronize()
+        amg.amg_destroy(h)
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_params(kind, k):
+    from oracle import polynomials as P
+    beta = P.optimal_beta(k)[0] if kind == 2 else None
+    a = P.a_star(k) if kind == 3 else None
+    return beta, a

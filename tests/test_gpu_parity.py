@@ -1,0 +1,324 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Bar (FP64): relative error <= 1e-12 per smoother application and per
+V-cycle, exact PCG iteration counts; integer/index data (Galerkin sparsity,
+aggregates) bit-exact.  Output buffers are NaN-filled before write-only calls
+so an unwritten entry fails the comparison.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_util import KINDS, dev, hierarchy, host, nan_vec, oracle_params, relerr, torch_cuda  # noqa: E402
+
+import workloads as W  # noqa: E402
+from oracle import amg as OA  # noqa: E402
+from oracle import smoothers as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _fv(shape, sigma, seed):
+    g = W.gaussian_random_field(shape, 4.0, seed)
+    return W.fv_diffusion(np.exp(sigma * g))
+
+
+@pytest.fixture(scope="module")
+def amg():
+    torch_cuda()
+    import paper_2407_09848_amd as amg
+    return amg
+
+
+# ---------------------------------------------------------------------------
+# smoother (one level), C1 workload: 10 consecutive applications per (kind, k)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", KINDS)
+def test_smoother_c1_ten_applications(amg, kind):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(1)
+    As = A.to_scipy()
+    Minv = S.l1_diagonal(As)
+    bd = dev(b)
+    with hierarchy(A) as h:
+        assert amg.amg_num_levels(h) == 1
+        for k in range(1, 7):
+            beta, a = oracle_params(kind, k)
+            x = nan_vec(A.n)
+            xo = None
+            for t in range(10):
+                amg.smoother_apply(h, 0, kind, k, bd, x, x_is_zero=(t == 0))
+                xo = S.smooth(As, Minv, b, xo, kind, k, beta, a)
+                torch.cuda.synchronize()
+                e = relerr(host(x), xo)
+                assert e <= TOL, (kind, k, t, e)
+
+
+@pytest.mark.parametrize("shape", [(13, 11, 9), (64, 3, 5), (7, 1, 1)])
+@pytest.mark.parametrize("kind", KINDS)
+def test_smoother_ragged_fv(amg, shape, kind):
+    """Several 64-row slices and a ragged tail; x0 = 0 and x0 random."""
+    torch = torch_cuda()
+    A = _fv(shape[::-1], 1.5, 5)
+    As = A.to_scipy()
+    Minv = S.l1_diagonal(As)
+    rng = np.random.default_rng(2)
+    b = rng.uniform(-1, 1, A.n)
+    x0 = rng.uniform(-1, 1, A.n)
+    with hierarchy(A, max_coarse=10**9) as h:
+        for k in (1, 2, 3, 6):
+            beta, a = oracle_params(kind, k)
+            x = nan_vec(A.n)
+            amg.smoother_apply(h, 0, kind, k, dev(b), x, x_is_zero=True)
+            xd = dev(x0)
+            amg.smoother_apply(h, 0, kind, k, dev(b), xd, x_is_zero=False)
+            torch.cuda.synchronize()
+            assert relerr(host(x), S.smooth(As, Minv, b, None, kind, k, beta, a)) <= TOL
+            assert relerr(host(xd), S.smooth(As, Minv, b, x0, kind, k, beta, a)) <= TOL
+
+
+def test_smoother_does_not_modify_b(amg):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=16)
+    bd = dev(b)
+    with hierarchy(A) as h:
+        for kind in KINDS:
+            x = nan_vec(A.n)
+            amg.smoother_apply(h, 0, kind, 5, bd, x, True)
+            amg.smoother_apply(h, 0, kind, 5, bd, x, False)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(bd), b)
+
+
+# ---------------------------------------------------------------------------
+# hierarchy: l1 diagonal, Galerkin operators, SpMV, transfers, coarse solve
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["poisson", "fv_odd", "q1", "batch"])
+def test_hierarchy_matches_oracle(amg, case):
+    torch = torch_cuda()
+    nbatch = 1
+    if case == "poisson":
+        A = W.poisson3d_7pt(32)
+        mc = 4096
+    elif case == "fv_odd":
+        A = _fv((14, 18, 20), 2.0, 3)
+        mc = 60
+    elif case == "q1":
+        A = W.q1_27pt(20)
+        mc = 200
+    else:
+        A = W.stack_block_diagonal([_fv((8, 8, 8), s, 10 + p) for p, s in enumerate((0.5, 1.0, 2.0))])
+        nbatch, mc = 3, 8
+    H = OA.build_hierarchy(A.to_scipy(), A.grid, nbatch=nbatch, max_coarse=mc)
+    with hierarchy(A, nbatch=nbatch, max_coarse=mc) as h:
+        assert amg.amg_num_levels(h) == len(H.levels)
+        for l, lv in enumerate(H.levels):
+            rp, cl, vl, mi = amg.amg_level_export(h, l)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(rp), lv.A.indptr)
+            assert np.array_equal(host(cl), lv.A.indices)
+            assert np.allclose(host(vl), lv.A.data, rtol=1e-14, atol=1e-14 * np.abs(lv.A.data).max())
+            assert np.allclose(host(mi), lv.Minv, rtol=1e-14, atol=0)
+            # SpMV
+            x = np.random.default_rng(l).uniform(-1, 1, lv.A.shape[0])
+            y = nan_vec(lv.A.shape[0])
+            amg.amg_spmv(h, l, dev(x), y)
+            torch.cuda.synchronize()
+            assert relerr(host(y), lv.A @ x) <= 1e-14
+        # transfers on every level
+        for l in range(len(H.levels) - 1):
+            lv = H.levels[l]
+            n, nc = lv.A.shape[0], H.levels[l + 1].A.shape[0]
+            rng = np.random.default_rng(7 + l)
+            b, x, xc = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, nc)
+            bc = nan_vec(nc)
+            amg.amg_restrict_residual(h, l, dev(b), dev(x), bc)
+            xd = dev(x)
+            amg.amg_prolong_add(h, l, dev(xc), xd)
+            torch.cuda.synchronize()
+            assert relerr(host(bc), lv.P.T @ (b - lv.A @ x)) <= 1e-14
+            assert np.array_equal(host(xd), x + lv.P @ xc)
+        # coarse solve
+        nL = H.levels[-1].A.shape[0]
+        bl = np.random.default_rng(3).uniform(-1, 1, nL)
+        xl = nan_vec(nL)
+        amg.amg_coarse_solve(h, dev(bl), xl)
+        torch.cuda.synchronize()
+        assert relerr(host(xl), OA.coarse_solve(H, bl)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1000, 4096, 130])
+def test_coarse_solve_padding(amg, n):
+    """Dense Cholesky / inverse path with n_L not a multiple of the 64-wide tile."""
+    torch = torch_cuda()
+    A = W.poisson3d_7pt(10) if n == 1000 else (W.poisson3d_7pt(16) if n == 4096 else _fv((2, 5, 13), 1.0, 1))
+    H = OA.build_hierarchy(A.to_scipy(), A.grid)
+    assert H.L == 0
+    b = np.random.default_rng(1).uniform(-1, 1, A.n)
+    with hierarchy(A) as h:
+        x = nan_vec(A.n)
+        amg.amg_coarse_solve(h, dev(b), x)
+        torch.cuda.synchronize()
+        assert relerr(host(x), OA.coarse_solve(H, b)) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# V-cycle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["poisson32", "fv_ragged"])
+@pytest.mark.parametrize("kind", KINDS)
+def test_vcycle_matches_oracle(amg, case, kind):
+    torch = torch_cuda()
+    if case == "poisson32":
+        A = W.poisson3d_7pt(32)
+        mc = 4096
+    else:
+        A = _fv((14, 18, 20), 2.0, 3)
+        mc = 60
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid, max_coarse=mc)
+    r = np.random.default_rng(4).uniform(-1, 1, A.n)
+    rd = dev(r)
+    with hierarchy(A, max_coarse=mc) as h:
+        for k in range(1, 7):
+            z = nan_vec(A.n)
+            amg.vcycle_apply(h, kind, k, rd, z)
+            torch.cuda.synchronize()
+            beta, _ = oracle_params(kind, k)
+            zo = OA.vcycle(H, r, kind, k, beta)
+            assert relerr(host(z), zo) <= TOL, (kind, k)
+        assert np.array_equal(host(rd), r)
+
+
+def test_vcycle_full_size_c2(amg):
+    """128^3 7-point Poisson, optimal 4th kind k = 4: the whole V-cycle output vs the oracle."""
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid)
+    with hierarchy(A) as h:
+        for kind in (2, 3):
+            z = nan_vec(A.n)
+            amg.vcycle_apply(h, kind, 4, dev(b), z)
+            torch.cuda.synchronize()
+            beta, _ = oracle_params(kind, 4)
+            assert relerr(host(z), OA.vcycle(H, b, kind, 4, beta)) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# PCG
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", KINDS)
+def test_pcg_iterations_match_oracle_32(amg, kind):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=32)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid)
+    with hierarchy(A) as h:
+        for k in range(1, 7):
+            x = nan_vec(A.n)
+            rc, it, rel, hist = amg.pcg_solve(h, kind, k, dev(b), x, True, 1e-8, 1000, False, True)
+            torch.cuda.synchronize()
+            beta, _ = oracle_params(kind, k)
+            ro, _ = OA.amg_pcg(As, b, A.grid, kind, k, H=H, beta=beta)
+            assert rc == amg.AMG_OK and it == ro.iters, (kind, k, it, ro.iters)
+            assert np.allclose(hist, ro.history, rtol=1e-6, atol=0)
+            assert relerr(host(x), ro.x) <= 1e-10
+
+
+def _golden_c2():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_pcg_iterations_128.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            kind, k, it, rel = line.split()
+            rows.append((int(kind), int(k), int(it), float(rel)))
+    return rows
+
+
+def test_pcg_iterations_full_size_c2(amg):
+    """128^3: iteration counts of every (kind, degree) equal the oracle's stored counts."""
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2)
+    bd = dev(b)
+    with hierarchy(A) as h:
+        for kind, k, it_o, rel_o in _golden_c2():
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, kind, k, bd, x, True, 1e-8, 1000)
+            torch.cuda.synchronize()
+            assert rc == amg.AMG_OK and it == it_o, (kind, k, it, it_o)
+            assert rel == pytest.approx(rel_o, rel=1e-6)
+            # true residual of the returned x (oracle SpMV)
+            xr = host(x)
+            assert np.linalg.norm(b - A.to_scipy() @ xr) <= 1.05e-8 * np.linalg.norm(b)
+
+
+def test_pcg_deterministic(amg):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=48)
+    with hierarchy(A) as h:
+        xs = []
+        for _ in range(2):
+            x = nan_vec(A.n)
+            amg.pcg_solve(h, 2, 4, dev(b), x)
+            torch.cuda.synchronize()
+            xs.append(host(x))
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_pcg_nonzero_start_and_flexible(amg):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=24)
+    As = A.to_scipy()
+    with hierarchy(A, max_coarse=512) as h:
+        x = dev(np.random.default_rng(1).uniform(-1, 1, A.n))
+        rc, it, rel, hist = amg.pcg_solve(h, 3, 3, dev(b), x, False, 1e-10, 200, True, True)
+        torch.cuda.synchronize()
+        assert rc == amg.AMG_OK and rel <= 1e-10 and hist[0] > 0.1
+        assert np.linalg.norm(b - As @ host(x)) <= 2e-10 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+# error paths (forced from the host)
+# ---------------------------------------------------------------------------
+def test_error_codes(amg):
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=16)
+    with hierarchy(A) as h:
+        x = nan_vec(A.n)
+        for kind, k in ((4, 2), (-1, 2), (2, 0), (2, 13)):
+            with pytest.raises(amg.AmgError) as ei:
+                amg.smoother_apply(h, 0, kind, k, dev(b), x, True)
+            assert ei.value.code == amg.AMG_EINVAL
+        with pytest.raises(amg.AmgError):
+            amg.smoother_apply(h, 5, 2, 2, dev(b), x, True)
+        bn = b.copy()
+        bn[17] = np.nan
+        with pytest.raises(amg.AmgError) as ei:
+            amg.pcg_solve(h, 2, 4, dev(bn), x)
+        assert ei.value.code == amg.AMG_ENAN
+        # 16^3 is a one-level hierarchy (V-cycle = exact solve): one iteration suffices
+        rc, it, rel, _ = amg.pcg_solve(h, 2, 4, dev(b), x, True, 1e-8, 1)
+        assert rc == amg.AMG_OK and it == 1 and rel < 1e-12
+        rc, it, rel, _ = amg.pcg_solve(h, 2, 4, dev(np.zeros(A.n)), x)
+        torch.cuda.synchronize()
+        assert rc == amg.AMG_OK and it == 0 and np.all(host(x) == 0)
+    A2, b2, _ = W.config_problem(2, size=24)
+    with hierarchy(A2, max_coarse=512) as h:
+        x = nan_vec(A2.n)
+        rc, it, rel, _ = amg.pcg_solve(h, 2, 4, dev(b2), x, True, 1e-8, 1)
+        assert rc == amg.AMG_NOT_CONVERGED and it == 1 and rel > 1e-8
+    bad = W.poisson3d_7pt(6)
+    r0, r1 = bad.row_ptr[10], bad.row_ptr[11]
+    d = r0 + int(np.where(bad.col[r0:r1] == 10)[0][0])  # diagonal entry of row 10
+    bad.val = bad.val.copy()
+    bad.val[d] = -6.0
+    with pytest.raises(amg.AmgError) as ei:
+        with hierarchy(bad):
+            pass
+    assert ei.value.code == amg.AMG_ENOTSPD
