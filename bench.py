@@ -82,6 +82,26 @@ def pcg_bytes(levels, ncp, nbatch, kind, k, iters, w=8):
     return setup + iters * per_it
 
 
+def measured_traffic(size):
+    """HBM bytes per launch of the fine-level fused step from the committed rocprofv3 counter
+    summary, or None when that summary does not cover this workload or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    import re
+    if size != 128:
+        return None
+    try:
+        src = open(os.path.join(ROOT, "paper_2407_09848_amd", "csrc", "kernels_sparse.hip")).read()
+        a = src.index("\n", src.index("// BEGIN fused-step")) + 1
+        digest = hashlib.sha256(src[a:src.index("// END fused-step")].encode()).hexdigest()[:16]
+        prof = open(os.path.join(ROOT, "profiles", "fused_step_poisson128.md")).read()
+        if re.search(r"sha256 prefix: (\w+)", prof).group(1) != digest:
+            return None
+        return int(re.search(r"traffic_bytes_per_launch: (\d+)", prof).group(1))
+    except (OSError, ValueError, AttributeError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,9 +179,25 @@ def main():
     fused_bytes = b_fused(nnz0, n0, True)
     achieved = fused_bytes / (t_fused_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
+                "frac": round(achieved / PEAK_HBM, 4), "traffic": measured_traffic(args.size),
                 "kernel": "k_fused<double,0,true> (fine level, 128^3)",
                 "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2)}
+
+    # ---- plain device copy of 1 GiB: measured copy bandwidth, and the reference
+    #      dispatch that calibrates the HBM byte counters of a profiling run ----
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    del src, dst
 
     # ---- variants: other kinds, FP32 hierarchy ----
     variants = {}

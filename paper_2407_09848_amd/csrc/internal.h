@@ -70,8 +70,19 @@ struct Level {
   int32_t* children = nullptr;    // [nc * 8] rows of each aggregate, ascending, -1 padded
 };
 
+// A captured V-cycle (one launch sequence for a given kind, degree and r/z buffers).
+struct GraphEntry {
+  int kind, k;
+  const void* r;
+  void* z;
+  hipGraphExec_t exec;
+};
+
 struct Handle {
   int nlevels = 0;
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;  // stream used only to capture V-cycles into graphs
+  std::vector<GraphEntry> graphs;
   int nbatch = 1;
   int precision = AMG_FP64;
   int max_coarse = 4096;
@@ -128,6 +139,9 @@ template <typename T>
 int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
                       T* x, double c, double w);
 template <typename T>
+int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
+                       T* r, T* x, double c1, double alpha, double c, double w1, double w2);
+template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c);
 template <typename T>
@@ -138,9 +152,10 @@ int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, con
 template <typename T>
 int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x);
 // transfers
+// b_c = P^T (b - A x); tmp (n entries) receives b - A x
 template <typename T>
 int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
-                    const T* x, T* bc);
+                    const T* x, T* tmp, T* bc);
 template <typename T>
 int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x);
 // vectors

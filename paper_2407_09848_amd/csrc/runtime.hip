@@ -1,5 +1,6 @@
 // Host runtime and C ABI: hierarchy setup, smoother dispatch, V-cycle and PCG.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -48,8 +49,17 @@ void free_vecs(Vecs<T>& v, bool own_bx) {
   v = Vecs<T>();
 }
 
+void drop_graphs(Handle* h) {
+  if (h->graphs.empty()) return;
+  hipDeviceSynchronize();  // no cached graph may still be executing when it is destroyed
+  for (auto& g : h->graphs) hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
 // Free everything the handle owns (the Handle object itself stays).
 void release(Handle* h) {
+  drop_graphs(h);
+  if (h->cap) hipStreamDestroy(h->cap);
   for (size_t l = 0; l < h->lv.size(); ++l) {
     Level& L = h->lv[l];
     hipFree(L.csr_ptr);
@@ -121,7 +131,15 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
     auto w = [&](int j) { return kind == AMG_OPTCHEB4 ? h->beta_at(l, k, j - 1) : 1.0; };
     const double c1 = (8.0 * 1 - 4.0) / (2.0 * 1 + 1.0);
     const T* rsrc;
-    if (xz) {
+    int j0 = 2;
+    if (xz && k >= 2) {
+      // steps 1 and 2 in one pass
+      const double alpha2 = (2.0 * 2 - 3.0) / (2.0 * 2 + 1.0), c2 = (8.0 * 2 - 4.0) / (2.0 * 2 + 1.0);
+      AMGP_TRY(launch_first2_zero<T>(s, 0, k > 2, A, minv, b, g[1 - cur], v.r, x, c1, alpha2, c2, w(1), w(2)));
+      rsrc = v.r;
+      cur = 1 - cur;
+      j0 = 3;
+    } else if (xz) {
       AMGP_TRY(launch_first_zero<T>(s, 0, k > 1, n, minv, b, g[cur], nullptr, x, c1, w(1)));
       rsrc = b;
     } else {
@@ -130,7 +148,7 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
       pending = w(1);
       if (k == 1) return launch_axpy<T>(s, n, pending, g[cur], x);
     }
-    for (int j = 2; j <= k; ++j) {
+    for (int j = j0; j <= k; ++j) {
       const double alpha = (2.0 * j - 3.0) / (2.0 * j + 1.0);
       const double c = (8.0 * j - 4.0) / (2.0 * j + 1.0);
       AMGP_TRY(launch_fused<T>(s, 0, j < k, A, minv, g[cur], g[1 - cur], rsrc, v.r, x, alpha, c, w(j), pending));
@@ -145,14 +163,23 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
   const double theta = (1.0 + a) / 2.0, delta = (1.0 - a) / 2.0;
   const double sigma1 = theta / delta;
   double rho_prev = 1.0 / sigma1;
-  if (xz) {
+  int j0 = 1;
+  if (xz && k >= 2) {
+    // steps 0 and 1 of Algorithm 1 in one pass
+    const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
+    AMGP_TRY(launch_first2_zero<T>(s, 1, k > 2, A, minv, b, g[1 - cur], v.r, x, theta, rho * rho_prev,
+                                   2.0 * rho / delta, 1.0, 1.0));
+    rho_prev = rho;
+    cur = 1 - cur;
+    j0 = 2;
+  } else if (xz) {
     AMGP_TRY(launch_first_zero<T>(s, 1, k > 1, n, minv, b, g[cur], v.r, x, theta, 1.0));
   } else {
     AMGP_TRY(launch_first_res<T>(s, 1, A, minv, b, x, v.r, g[cur], theta));
     pending = 1.0;
     if (k == 1) return launch_axpy<T>(s, n, pending, g[cur], x);
   }
-  for (int j = 1; j <= k - 1; ++j) {
+  for (int j = j0; j <= k - 1; ++j) {
     const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
     AMGP_TRY(launch_fused<T>(s, 1, j < k - 1, A, minv, g[cur], g[1 - cur], v.r, v.r, x, rho * rho_prev,
                              2.0 * rho / delta, 1.0, pending));
@@ -177,7 +204,7 @@ int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s) {
   Level& L = h->lv[l];
   Vecs<T>& vc = Prec<T>::v(h->lv[l + 1]);
   AMGP_TRY(smooth<T>(h, l, kind, k, b, x, true, s));
-  AMGP_TRY(launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, vc.b));
+  AMGP_TRY(launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, Prec<T>::v(L).r, vc.b));
   AMGP_TRY(vcycle<T>(h, l + 1, kind, k, vc.b, vc.x, s));
   AMGP_TRY(launch_prolong<T>(s, L.n, L.agg, vc.x, x));
   return smooth<T>(h, l, kind, k, b, x, false, s);
@@ -191,6 +218,37 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
   return vcycle<double>(h, 0, kind, k, r, z, s);
+}
+
+// The V-cycle as one HIP graph: captured on the handle's own stream the first
+// time a (kind, degree, r, z) combination is seen, then replayed on the
+// caller's stream.  The coarse levels are launch-latency bound; a graph
+// removes the per-launch host overhead.  The kernel arguments (including the
+// beta weights) are baked in, so changing beta drops the cached graphs.
+int vcycle_run(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s) {
+  if (!h->use_graphs) return vcycle_top(h, kind, k, r, z, s);
+  for (auto& g : h->graphs)
+    if (g.kind == kind && g.k == k && g.r == r && g.z == z) {
+      AMGP_HIP(hipGraphLaunch(g.exec, s));
+      return AMG_OK;
+    }
+  if (h->graphs.size() >= 32) drop_graphs(h);
+  if (!h->cap) AMGP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  AMGP_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+  const int rc = vcycle_top(h, kind, k, r, z, h->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap, &graph);
+  if (rc != AMG_OK || e != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return rc != AMG_OK ? rc : AMG_EHIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ei != hipSuccess) return AMG_EHIP;
+  h->graphs.push_back(GraphEntry{kind, k, r, z, exec});
+  AMGP_HIP(hipGraphLaunch(exec, s));
+  return AMG_OK;
 }
 
 int check_kind_degree(int kind, int degree) {
@@ -221,6 +279,10 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   h->nbatch = o->nbatch > 0 ? o->nbatch : 1;
   h->max_coarse = o->max_coarse > 0 ? o->max_coarse : 4096;
   h->precision = o->precision;
+  {
+    const char* e = std::getenv("AMGP_NO_GRAPH");
+    h->use_graphs = !(e && e[0] == '1');
+  }
   AMGP_TRY(dalloc(&h->dflag, F_NFLAG));
   AMGP_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int) * F_NFLAG, s));
   // level 0: library-owned copy of the CSR matrix
@@ -362,7 +424,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   if (hist) hist[0] = rel0;
   *relres = rel0;
   if (rel0 <= rtol) return AMG_OK;
-  AMGP_TRY(vcycle_top(h, kind, k, r, z, s));
+  AMGP_TRY(vcycle_run(h, kind, k, r, z, s));
   AMGP_TRY(sum_dot(h, s, RED_RZ0, r, z, nullptr, nullptr, n));
   AMGP_TRY(launch_copy<double>(s, n, z, p));
   for (int it = 1; it <= maxit; ++it) {
@@ -380,7 +442,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
     if (hist) hist[it] = rel;
     if (rel <= rtol) return AMG_OK;
     if (it == maxit) break;
-    AMGP_TRY(vcycle_top(h, kind, k, r, z, s));
+    AMGP_TRY(vcycle_run(h, kind, k, r, z, s));
     if (flex)
       AMGP_TRY(sum_dot(h, s, RED_BETA_FLEX, r, z, rold, z, n));
     else
@@ -477,6 +539,7 @@ int amg_set_beta(amg_handle* h, int degree, int level, const double* h_beta) {
   if (level < -1 || level >= H.nlevels) return AMG_EINVAL;
   for (int j = 0; j < degree; ++j)
     if (!std::isfinite(h_beta[j])) return AMG_EINVAL;
+  amgp::drop_graphs(&H);
   for (int l = 0; l < H.nlevels; ++l) {
     if (level != -1 && l != level) continue;
     for (int j = 0; j < degree; ++j) H.beta_at(l, degree, j) = h_beta[j];
@@ -487,6 +550,7 @@ int amg_set_beta(amg_handle* h, int degree, int level, const double* h_beta) {
 int amg_reset_beta(amg_handle* h) {
   if (!h) return AMG_EINVAL;
   Handle& H = h->impl;
+  amgp::drop_graphs(&H);
   for (int l = 0; l < H.nlevels; ++l)
     for (int k = 1; k <= AMG_MAX_DEGREE; ++k)
       for (int j = 0; j < k; ++j) H.beta_at(l, k, j) = kOptBeta[k][j];
@@ -508,8 +572,8 @@ int smoother_apply(amg_handle* h, int level, int kind, int degree, const double*
 int amg_restrict_residual(amg_handle* h, int level, const double* d_b, const double* d_x, double* d_bc,
                           void* stream) {
   if (!h || !d_b || !d_x || !d_bc || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;
-  const amgp::Level& L = h->impl.lv[level];
-  return amgp::launch_restrict<double>((hipStream_t)stream, L.A64, L.nc, L.children, d_b, d_x, d_bc);
+  amgp::Level& L = h->impl.lv[level];
+  return amgp::launch_restrict<double>((hipStream_t)stream, L.A64, L.nc, L.children, d_b, d_x, L.v64.r, d_bc);
 }
 
 int amg_prolong_add(amg_handle* h, int level, const double* d_xc, double* d_x, void* stream) {
@@ -526,7 +590,7 @@ int amg_coarse_solve(amg_handle* h, const double* d_b, double* d_x, void* stream
 int vcycle_apply(amg_handle* h, int kind, int degree, const double* d_r, double* d_z, void* stream) {
   if (!h || !d_r || !d_z) return AMG_EINVAL;
   AMGP_TRY(amgp::check_kind_degree(kind, degree));
-  return amgp::vcycle_top(&h->impl, kind, degree, d_r, d_z, (hipStream_t)stream);
+  return amgp::vcycle_run(&h->impl, kind, degree, d_r, d_z, (hipStream_t)stream);
 }
 
 int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_x, int x_is_zero, double rtol,

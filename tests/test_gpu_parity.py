@@ -195,6 +195,68 @@ def test_vcycle_matches_oracle(amg, case, kind):
         assert np.array_equal(host(rd), r)
 
 
+def test_vcycle_graph_replays_and_beta_change(amg):
+    """The V-cycle is captured once per (kind, degree, buffers) and replayed: every replay, with
+    eager work in between, equals the oracle; a new beta drops the captured graph."""
+    torch = torch_cuda()
+    A = W.poisson3d_7pt(24)
+    H = OA.build_hierarchy(A.to_scipy(), A.grid, max_coarse=300)
+    r = np.random.default_rng(8).uniform(-1, 1, A.n)
+    rd = dev(r)
+    beta, _ = oracle_params(2, 3)
+    zo = OA.vcycle(H, r, 2, 3, beta)
+    with hierarchy(A, max_coarse=300) as h:
+        z = nan_vec(A.n)
+        for rep in range(4):
+            z.fill_(float("nan"))
+            amg.vcycle_apply(h, 2, 3, rd, z)
+            xs = nan_vec(A.n)
+            amg.smoother_apply(h, 0, 1, 2, rd, xs, True)  # eager work between replays
+            torch.cuda.synchronize()
+            assert relerr(host(z), zo) <= TOL, rep
+        nb = [1.1, 0.9, 1.3]
+        amg.amg_set_beta(h, 3, -1, nb)
+        amg.vcycle_apply(h, 2, 3, rd, z)
+        torch.cuda.synchronize()
+        assert relerr(host(z), OA.vcycle(H, r, 2, 3, nb)) <= TOL
+        amg.amg_set_beta(h, 3, 1, [1.0, 1.0, 1.0])  # level 1 only
+        amg.vcycle_apply(h, 2, 3, rd, z)
+        torch.cuda.synchronize()
+        per_level = [nb, [1.0, 1.0, 1.0]] + [nb] * (len(H.levels) - 2)
+        assert relerr(host(z), OA.vcycle(H, r, 2, 3, None, betas_by_level=per_level)) <= TOL
+        amg.amg_reset_beta(h)
+        amg.vcycle_apply(h, 2, 3, rd, z)
+        torch.cuda.synchronize()
+        assert relerr(host(z), zo) <= TOL
+
+
+def test_fp32_hierarchy(amg):
+    """FP32 hierarchy inside FP64 CG (parity unpinned: no exact FP32 answer); bounded instead:
+    converges to 1e-8 in the FP64 iteration count (+-1), true FP64 residual within 2e-8, and the
+    FP32 V-cycle differs from the FP64 oracle V-cycle by no more than FP32 rounding allows."""
+    torch = torch_cuda()
+    g = W.gaussian_random_field((48, 48, 48), 8.0, W.SEED_GRF)
+    A = W.fv_diffusion(np.exp(g))
+    b = W.rhs_uniform(A.n, W.SEED_RHS + 3)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid, max_coarse=4096)
+    ro, _ = OA.amg_pcg(As, b, A.grid, 2, 4, H=H)
+    with hierarchy(A, precision=amg.AMG_FP32) as h:
+        z = nan_vec(A.n)
+        amg.vcycle_apply(h, 2, 4, dev(b), z)
+        torch.cuda.synchronize()
+        e_v = relerr(host(z), OA.vcycle(H, b, 2, 4))
+        assert e_v <= 1e-5
+        for flexible in (False, True):
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, 2, 4, dev(b), x, True, 1e-8, 200, flexible)
+            torch.cuda.synchronize()
+            assert rc == amg.AMG_OK and abs(it - ro.iters) <= 1
+            xr = host(x)
+            assert np.linalg.norm(b - As @ xr) <= 2e-8 * np.linalg.norm(b)
+            assert relerr(xr, ro.x) <= 1e-6
+
+
 def test_vcycle_full_size_c2(amg):
     """128^3 7-point Poisson, optimal 4th kind k = 4: the whole V-cycle output vs the oracle."""
     torch = torch_cuda()
