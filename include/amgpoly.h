@@ -171,6 +171,64 @@ int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_
               double rtol, int maxit, int flexible, int* h_iters, double* h_relres,
               double* h_hist, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Differentiable V-cycle and the learned optimal-4th-kind weights.
+ *
+ * Weight table layout (device, float64): d_beta[(p * nlevels + l) * degree + j - 1]
+ * is beta_j of the degree-`degree` optimal 4th-kind smoother (eq. polsmootheropt)
+ * used for stacked problem p on level l (pre- and post-smoothing alike).
+ * These calls always use the optimal 4th kind.  Vectors are float64 at the
+ * boundary; the cycle runs in the handle's precision.
+ * ------------------------------------------------------------------------- */
+/* Bytes of checkpoint storage one differentiable V-cycle needs (caller allocates it). */
+int amg_ckpt_bytes(const amg_handle* h, int64_t* h_bytes);
+
+/* z = B(beta) r (the V-cycle of eq. amg with per-problem, per-level weights), saving
+ * each level's smoother inputs (the level right-hand side and the post-smoothing
+ * residual) into d_ckpt.  d_r is read only. */
+int vcycle_fwd_ckpt(amg_handle* h, int degree, const double* d_beta, const double* d_r, double* d_z,
+                    void* d_ckpt, void* stream);
+
+/* Adjoint of vcycle_fwd_ckpt: given d_gz = dL/dz, writes d_gr = dL/dr (= B(beta) d_gz, the
+ * V-cycle being symmetric) and ADDS dL/dbeta into d_gbeta (layout of d_beta).  Each
+ * smoother's correction is a symmetric operator in M^{-1}A, so its adjoint is the same
+ * recurrence run on the incoming adjoint; dL/dbeta_j is the dot product of that run's
+ * j-th direction with the checkpointed recurrence input.  The SpMV is reused (A = A^T). */
+int vcycle_bwd(amg_handle* h, int degree, const double* d_beta, const void* d_ckpt, const double* d_gz,
+               double* d_gr, double* d_gbeta, void* stream);
+
+/* Residual-reduction loss of two V-cycle iterations from x = 0 on d_b:
+ *   r_0 = b, r_1 = r_0 - A B r_0, r_2 = r_1 - A B r_1,
+ *   loss = mean over stacked problems p of ||r_2,p|| / ||r_0,p||,
+ * its gradient d_gbeta = d loss / d beta (overwritten), and h_loss[0] = loss,
+ * h_loss[1 + p] = ratio of problem p (host, nbatch + 1 entries).  Synchronises. */
+int amg_train_loss_grad(amg_handle* h, int degree, const double* d_beta, const double* d_b, double* h_loss,
+                        double* d_gbeta, void* stream);
+
+/* Eight features per (stacked problem p, smoothing level l < nlevels-1), row (p * (nlevels-1) + l)
+ * of d_feat (float32): degree/6, l/(nlevels-1), 1 - lambda_max(M^{-1}A_l) estimated by 20
+ * power iterations from the ones vector (the margin below the l1-Jacobi bound rho <= 1),
+ * (nnz_l/n_l)/27, log2(rows per problem)/24, h_sigma[p], n_{l+1}/n_l, and the mean over
+ * rows of sum_{j!=i}|a_ij| / a_ii.  Synchronises. */
+int amg_level_features(amg_handle* h, int degree, const double* h_sigma, float* d_feat, void* stream);
+
+/* MLP 8 -> 64 -> 64 -> 6 (tanh hidden units, output scaled by 0.1), float32.
+ * Parameters d_params[mlp_num_params()] = W1[64][8], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
+ * mlp_fwd: d_y[batch][6] from d_x[batch][8]; d_cache[batch][128] keeps the hidden activations.
+ * mlp_bwd: d_gparams = d(sum of d_gy . y)/d params (overwritten); d_work[2 * batch * 64].
+ * mlp_adam: one bias-corrected Adam step (step >= 1) on d_params.  1 <= batch <= 256. */
+int mlp_num_params(void);
+int mlp_fwd(const float* d_params, const float* d_x, int batch, float* d_y, float* d_cache, void* stream);
+int mlp_bwd(const float* d_params, const float* d_x, int batch, const float* d_cache, const float* d_gy,
+            float* d_gparams, float* d_work, void* stream);
+int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, int step, float lr, float b1,
+             float b2, float eps, void* stream);
+
+/* d_valid[q] = 1 when the weighted 4th-kind polynomial of row q of d_beta (count rows of
+ * `degree` weights) stays inside Pi_k (eq. polspace): |p(x)| < 1 at x = m/ngrid, m = 1..ngrid
+ * (p(0) = 1 holds for any weights); else 0.  Used to fall back to the tabulated weights. */
+int amg_beta_valid(const double* d_beta, int count, int degree, int ngrid, int* d_valid, void* stream);
+
 /* Human-readable name of a return code (static storage). */
 const char* amg_strerror(int code);
 

@@ -16,7 +16,9 @@ __all__ = [
     "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info",
     "amg_level_export", "amg_default_beta", "amg_default_astar", "amg_set_beta", "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
-    "vcycle_apply", "pcg_solve", "amg_strerror",
+    "vcycle_apply", "pcg_solve", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
+    "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_adam",
+    "amg_beta_valid", "VCycleFunction",
     "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
     "AMG_EBREAKDOWN", "AMG_ENAN", "AMG_ECAPACITY", "AMG_L1JAC", "AMG_CHEB4", "AMG_OPTCHEB4",
     "AMG_OPTCHEB1", "AMG_FP64", "AMG_FP32", "AMG_MAX_DEGREE",
@@ -59,6 +61,16 @@ _SIGS = {
     "pcg_solve": (_I, [_P, _I, _I, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
                        ctypes.POINTER(_D), _P]),
     "amg_strerror": (ctypes.c_char_p, [_I]),
+    "amg_ckpt_bytes": (_I, [_P, ctypes.POINTER(_I64)]),
+    "vcycle_fwd_ckpt": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "vcycle_bwd": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
+    "amg_train_loss_grad": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D), _P, _P]),
+    "amg_level_features": (_I, [_P, _I, ctypes.POINTER(_D), _P, _P]),
+    "mlp_num_params": (_I, []),
+    "mlp_fwd": (_I, [_P, _P, _I, _P, _P, _P]),
+    "mlp_bwd": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
+    "mlp_adam": (_I, [_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "amg_beta_valid": (_I, [_P, _I, _I, _I, _P, _P]),
 }
 
 
@@ -229,3 +241,127 @@ def pcg_solve(h, kind, degree, b, x, x_is_zero=True, rtol=1e-8, maxit=1000, flex
                          ctypes.byref(rel), hist, _stream())
     _check(rc, "pcg_solve", allow=(AMG_OK, AMG_NOT_CONVERGED))
     return rc, it.value, rel.value, ([hist[i] for i in range(it.value + 1)] if history else None)
+
+
+# ---------------------------------------------------------------------------
+# differentiable V-cycle and learned weights
+# ---------------------------------------------------------------------------
+def amg_ckpt_bytes(h) -> int:
+    v = _I64()
+    _check(lib().amg_ckpt_bytes(h, ctypes.byref(v)), "amg_ckpt_bytes")
+    return v.value
+
+
+def vcycle_fwd_ckpt(h, degree, beta, r, z, ckpt):
+    """z = B(beta) r saving checkpoints; beta: float64 device [nbatch * nlevels * degree]."""
+    import torch
+    n, _ = amg_level_info(h, 0)
+    return _check(lib().vcycle_fwd_ckpt(h, degree, _ptr(beta, torch.float64, name="beta"),
+                                        _ptr(r, torch.float64, n, "r"), _ptr(z, torch.float64, n, "z"),
+                                        _ptr(ckpt, name="ckpt"), _stream()), "vcycle_fwd_ckpt")
+
+
+def vcycle_bwd(h, degree, beta, ckpt, gz, gr, gbeta):
+    import torch
+    n, _ = amg_level_info(h, 0)
+    return _check(lib().vcycle_bwd(h, degree, _ptr(beta, torch.float64, name="beta"), _ptr(ckpt, name="ckpt"),
+                                   _ptr(gz, torch.float64, n, "gz"), _ptr(gr, torch.float64, n, "gr"),
+                                   _ptr(gbeta, torch.float64, beta.numel(), "gbeta"), _stream()), "vcycle_bwd")
+
+
+def amg_train_loss_grad(h, degree, beta, b, gbeta, nbatch):
+    """Returns (loss, per-problem ratios); gbeta (device float64, layout of beta) is overwritten."""
+    import torch
+    n, _ = amg_level_info(h, 0)
+    out = (_D * (nbatch + 1))()
+    _check(lib().amg_train_loss_grad(h, degree, _ptr(beta, torch.float64, name="beta"), _ptr(b, torch.float64, n, "b"),
+                                     out, _ptr(gbeta, torch.float64, beta.numel(), "gbeta"), _stream()),
+           "amg_train_loss_grad")
+    return out[0], [out[1 + p] for p in range(nbatch)]
+
+
+def amg_level_features(h, degree, sigma):
+    """float32 device tensor [nbatch * (nlevels - 1), 8] of per-level features."""
+    import torch
+    L = amg_num_levels(h)
+    sig = (_D * len(sigma))(*[float(s) for s in sigma])
+    feat = torch.empty((len(sigma) * (L - 1), 8), dtype=torch.float32, device="cuda")
+    _check(lib().amg_level_features(h, degree, sig, _ptr(feat), _stream()), "amg_level_features")
+    return feat
+
+
+def mlp_num_params() -> int:
+    return lib().mlp_num_params()
+
+
+def mlp_fwd(params, x, y, cache):
+    import torch
+    B = x.shape[0]
+    return _check(lib().mlp_fwd(_ptr(params, torch.float32), _ptr(x, torch.float32), B, _ptr(y, torch.float32),
+                                _ptr(cache, torch.float32), _stream()), "mlp_fwd")
+
+
+def mlp_bwd(params, x, cache, gy, gparams, work):
+    import torch
+    B = x.shape[0]
+    return _check(lib().mlp_bwd(_ptr(params, torch.float32), _ptr(x, torch.float32), B, _ptr(cache, torch.float32),
+                                _ptr(gy, torch.float32), _ptr(gparams, torch.float32), _ptr(work, torch.float32),
+                                _stream()), "mlp_bwd")
+
+
+def mlp_adam(params, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    import torch
+    n = params.numel()
+    return _check(lib().mlp_adam(_ptr(params, torch.float32, n), _ptr(g, torch.float32, n), _ptr(m, torch.float32, n),
+                                 _ptr(v, torch.float32, n), n, int(step), lr, b1, b2, eps, _stream()), "mlp_adam")
+
+
+def amg_beta_valid(beta, degree, ngrid=4096):
+    """int32 device tensor: 1 where row q of beta ([count, degree] float64) keeps |p| < 1 on (0, 1]."""
+    import torch
+    count = beta.numel() // degree
+    valid = torch.empty(count, dtype=torch.int32, device="cuda")
+    _check(lib().amg_beta_valid(_ptr(beta, torch.float64), count, degree, ngrid, _ptr(valid), _stream()),
+           "amg_beta_valid")
+    return valid
+
+
+def _vcycle_function():
+    import torch
+
+    class VCycleFunction(torch.autograd.Function):
+        """z = B(beta) r as an autograd function: forward runs vcycle_fwd_ckpt (checkpoints kept
+        on the context), backward runs the hand-written adjoint vcycle_bwd."""
+
+        @staticmethod
+        def forward(ctx, beta, r, handle, degree):
+            ck = torch.empty(amg_ckpt_bytes(handle), dtype=torch.uint8, device="cuda")
+            z = torch.empty_like(r)
+            vcycle_fwd_ckpt(handle, degree, beta.contiguous(), r.contiguous(), z, ck)
+            ctx.save_for_backward(beta)
+            ctx.ck = ck
+            ctx.handle, ctx.degree = handle, degree
+            return z
+
+        @staticmethod
+        def backward(ctx, gz):
+            (beta,) = ctx.saved_tensors
+            gbeta = torch.zeros_like(beta)
+            gr = torch.empty_like(gz)
+            vcycle_bwd(ctx.handle, ctx.degree, beta.contiguous(), ctx.ck, gz.contiguous(), gr, gbeta)
+            ctx.ck = None
+            return gbeta, gr, None, None
+
+    return VCycleFunction
+
+
+class _LazyVCycle:
+    _cls = None
+
+    def apply(self, *args):
+        if _LazyVCycle._cls is None:
+            _LazyVCycle._cls = _vcycle_function()
+        return _LazyVCycle._cls.apply(*args)
+
+
+VCycleFunction = _LazyVCycle()

@@ -30,6 +30,14 @@ struct Ell {
   T* val = nullptr;         // [padded]
 };
 
+// Per-problem smoother weights for stacked problems: the weight of row i is
+// v[(i / rpp) * stride] when v is not null (otherwise the launch's scalar).
+struct Wt {
+  const double* v = nullptr;
+  int rpp = 1;
+  int stride = 0;
+};
+
 template <typename T>
 struct EllView {
   const int32_t* __restrict__ sptr;
@@ -78,8 +86,27 @@ struct GraphEntry {
   hipGraphExec_t exec;
 };
 
+// Workspace of the differentiable V-cycle (allocated on first use).
+template <typename T>
+struct AdjVecs {
+  T *u = nullptr, *xmid = nullptr, *xpre = nullptr, *res = nullptr, *xin = nullptr, *bout = nullptr;
+};
+
 struct Handle {
   int nlevels = 0;
+  // per-problem weights for AMG_OPTCHEB4 while a differentiable V-cycle runs:
+  // dbeta[(p * nlevels + l) * dbeta_k + j - 1], else null (host table used)
+  const double* dbeta = nullptr;
+  int dbeta_k = 0;
+  std::vector<int64_t> ck_off;  // checkpoint offset (elements) of level l: [pre n_l][post n_l]
+  int64_t ck_count = 0;         // elements per V-cycle checkpoint
+  bool train_ready = false;
+  std::vector<AdjVecs<double>> adj64;
+  std::vector<AdjVecs<float>> adj32;
+  void* tr_buf = nullptr;       // training driver vectors and checkpoints
+  double* tr_sq = nullptr;      // [2 * nbatch] squared norms
+  double* tr_loss = nullptr;    // [1 + nbatch]
+  double* tr_partial = nullptr; // segmented-reduction partials
   bool use_graphs = true;
   hipStream_t cap = nullptr;  // stream used only to capture V-cycles into graphs
   std::vector<GraphEntry> graphs;
@@ -137,16 +164,18 @@ int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r
 // smoother steps
 template <typename T>
 int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
-                      T* x, double c, double w);
+                      T* x, double c, double w, Wt wv = Wt());
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
-                       T* r, T* x, double c1, double alpha, double c, double w1, double w2);
+                       T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v = Wt(),
+                       Wt w2v = Wt());
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c);
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
-                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev);
+                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv = Wt(),
+                 Wt wpv = Wt());
 template <typename T>
 int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew);
 template <typename T>
@@ -160,7 +189,7 @@ template <typename T>
 int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x);
 // vectors
 template <typename T>
-int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y);  // y += a x
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av = Wt());  // y += a x
 template <typename T>
 int launch_copy(hipStream_t s, int64_t n, const T* x, T* y);
 template <typename T>
@@ -183,6 +212,31 @@ int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double
 int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag);
 enum ReduceMode { RED_BB = 0, RED_RZ0, RED_ALPHA, RED_RR, RED_BETA, RED_BETA_FLEX };
 int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag);
+
+// ---- differentiable V-cycle and learned-beta network (kernels_train.hip) ----
+// out[p * ostride] (+)= (a_p, b_p) over segment p (b = nullptr: |a_p|^2); partial >= 64 * nseg doubles
+template <typename T>
+int launch_seg_dot(hipStream_t s, int nseg, int64_t rpp, const T* a, const T* b, double* partial, double* out,
+                   int ostride, bool acc);
+template <typename T>
+int launch_loss_seed(hipStream_t s, int64_t n, int64_t rpp, int P, const double* sq, const T* r2, T* g);
+int launch_loss_value(hipStream_t s, int P, const double* sq, double* out);
+template <typename T>
+int launch_neg(hipStream_t s, int64_t n, const T* x, T* y);
+template <typename T>
+int launch_prolong_set(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x);
+template <typename T>
+int launch_restrict_sum(hipStream_t s, int64_t nc, const int32_t* children, const T* x, T* yc);
+int launch_mlp_fwd(hipStream_t s, int B, const float* W, const float* X, float* Y, float* cache);
+int launch_mlp_bwd(hipStream_t s, int B, const float* W, const float* X, const float* cache, const float* dY,
+                   float* G, float* work);
+int launch_adam(hipStream_t s, int n, float* W, const float* G, float* m, float* v, float lr, float b1, float b2,
+                float eps, float c1, float c2);
+int launch_beta_valid(hipStream_t s, int count, int k, const double* beta, int ngrid, int* valid);
+int mlp_num_params();
+int launch_mul(hipStream_t s, int64_t n, const double* a, const double* x, double* y);
+int launch_offdiag_ratio(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                         const double* minv, double* out);
 
 // ---- setup kernels (kernels_setup.hip) ----
 // row_ptr monotone from 0 to nnz, columns strictly increasing within a row and in [0, n)

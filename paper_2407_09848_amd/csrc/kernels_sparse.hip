@@ -32,6 +32,11 @@ __device__ __forceinline__ int64_t logical_block() {
 __device__ __forceinline__ int64_t row_index() { return logical_block() * kBlock + threadIdx.x; }
 
 template <typename T>
+__device__ __forceinline__ T wsel(const Wt& w, T scalar, int64_t i) {
+  return w.v ? (T)w.v[(int)i / w.rpp * w.stride] : scalar;
+}
+
+template <typename T>
 __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restrict__ x) {
   // every lane of the wavefront is in the same slice: read its bounds once, as scalars
   const int s = __builtin_amdgcn_readfirstlane((int)(row >> 6));
@@ -101,9 +106,11 @@ template <typename T, int MODE, bool STORE>
 __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                   const T* __restrict__ gold, T* __restrict__ gnew,
                                                   const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
-                                                  T wprev) {
+                                                  T wprev, Wt wv, Wt wpv) {
   const int64_t i = row_index();
   if (i >= n) return;
+  w = wsel(wv, w, i);
+  wprev = wsel(wpv, wprev, i);
   const T ag = ell_dot(A, i, gold);
   const T mi = minv[i];
   const T go = gold[i];
@@ -123,9 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
 template <typename T, int MODE, bool STORE>
 __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __restrict__ minv,
                                                        const T* __restrict__ b, T* __restrict__ g,
-                                                       T* __restrict__ r, T* __restrict__ x, T c, T w) {
+                                                       T* __restrict__ r, T* __restrict__ x, T c, T w, Wt wv) {
   const int64_t i = row_index();
   if (i >= n) return;
+  w = wsel(wv, w, i);
   const T mi = minv[i];
   if (MODE == 0) {
     const T gi = c * (mi * b[i]);
@@ -152,9 +160,11 @@ template <typename T, int MODE, bool STORE>
 __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                         const T* __restrict__ b, T* __restrict__ gnew,
                                                         T* __restrict__ r, T* __restrict__ x, T c1, T alpha, T c,
-                                                        T w1, T w2) {
+                                                        T w1, T w2, Wt w1v, Wt w2v) {
   const int64_t i = row_index();
   if (i >= n) return;
+  w1 = wsel(w1v, w1, i);
+  w2 = wsel(w2v, w2, i);
   const int s = __builtin_amdgcn_readfirstlane((int)(i >> 6));
   const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
@@ -258,10 +268,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t* __
 // Vector kernels
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
+__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y, Wt av) {
   const int64_t i = row_index();
   if (i >= n) return;
-  y[i] = y[i] + a * x[i];
+  y[i] = y[i] + wsel(av, a, i) * x[i];
 }
 
 template <typename T>
@@ -443,32 +453,32 @@ int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r
 
 template <typename T>
 int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
-                      T* x, double c, double w) {
+                      T* x, double c, double w, Wt wv) {
   dim3 gr(xcd_grid(n)), bl(kBlock);
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first_zero<T, 0, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+    hipLaunchKernelGGL((k_first_zero<T, 0, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_first_zero<T, 0, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+    hipLaunchKernelGGL((k_first_zero<T, 0, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
   else if (store)
-    hipLaunchKernelGGL((k_first_zero<T, 1, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+    hipLaunchKernelGGL((k_first_zero<T, 1, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
   else
-    hipLaunchKernelGGL((k_first_zero<T, 1, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w);
+    hipLaunchKernelGGL((k_first_zero<T, 1, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
   return LAUNCH_OK();
 }
 
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
-                       T* r, T* x, double c1, double alpha, double c, double w1, double w2) {
+                       T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v, Wt w2v) {
   dim3 gr(xcd_grid(A.n)), bl(kBlock);
   const T a1 = (T)c1, a2 = (T)alpha, a3 = (T)c, a4 = (T)w1, a5 = (T)w2;
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
   else if (store)
-    hipLaunchKernelGGL((k_first2_zero<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
   else
-    hipLaunchKernelGGL((k_first2_zero<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
   return LAUNCH_OK();
 }
 
@@ -485,21 +495,21 @@ int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, co
 
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
-                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev) {
+                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv) {
   dim3 gr(xcd_grid(A.n)), bl(kBlock);
   const T a_ = (T)alpha, c_ = (T)c, w_ = (T)w, wp_ = (T)wprev;
   if (mode == 0 && store)
     hipLaunchKernelGGL((k_fused<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
-                       w_, wp_);
+                       w_, wp_, wv, wpv);
   else if (mode == 0)
     hipLaunchKernelGGL((k_fused<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
-                       c_, w_, wp_);
+                       c_, w_, wp_, wv, wpv);
   else if (store)
     hipLaunchKernelGGL((k_fused<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
-                       w_, wp_);
+                       w_, wp_, wv, wpv);
   else
     hipLaunchKernelGGL((k_fused<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
-                       c_, w_, wp_);
+                       c_, w_, wp_, wv, wpv);
   return LAUNCH_OK();
 }
 
@@ -530,8 +540,8 @@ int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T*
 }
 
 template <typename T>
-int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y) {
-  hipLaunchKernelGGL(k_axpy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, (T)a, x, y);
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av) {
+  hipLaunchKernelGGL(k_axpy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, (T)a, x, y, av);
   return LAUNCH_OK();
 }
 
@@ -610,18 +620,18 @@ int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
   template int launch_spmv<T>(hipStream_t, const Ell<T>&, const T*, T*);                                      \
   template int launch_residual<T>(hipStream_t, const Ell<T>&, const T*, const T*, T*);                        \
   template int launch_first_zero<T>(hipStream_t, int, bool, int64_t, const T*, const T*, T*, T*, T*, double,   \
-                                    double);                                                                  \
+                                    double, Wt);                                                              \
   template int launch_first2_zero<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, T*, T*,    \
-                                     double, double, double, double, double);                                 \
+                                     double, double, double, double, double, Wt, Wt);                         \
   template int launch_first_res<T>(hipStream_t, int, const Ell<T>&, const T*, const T*, const T*, T*, T*,      \
                                    double);                                                                   \
   template int launch_fused<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, const T*, T*, T*,  \
-                               double, double, double, double);                                               \
+                               double, double, double, double, Wt, Wt);                                       \
   template int launch_jacobi<T>(hipStream_t, const Ell<T>&, const T*, const T*, const T*, T*);                \
   template int launch_jacobi_zero<T>(hipStream_t, int64_t, const T*, const T*, T*);                           \
   template int launch_restrict<T>(hipStream_t, const Ell<T>&, int64_t, const int32_t*, const T*, const T*, T*, T*); \
   template int launch_prolong<T>(hipStream_t, int64_t, const int32_t*, const T*, T*);                         \
-  template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*);                                    \
+  template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*, Wt);                                \
   template int launch_copy<T>(hipStream_t, int64_t, const T*, T*);                                           \
   template int launch_fill<T>(hipStream_t, int64_t, T, T*);                                                   \
   template int launch_pad_in<T>(hipStream_t, int, int64_t, int64_t, const T*, double*);                       \
@@ -631,5 +641,6 @@ INST(double)
 INST(float)
 template int launch_cast<double, float>(hipStream_t, int64_t, const double*, float*);
 template int launch_cast<float, double>(hipStream_t, int64_t, const float*, double*);
+template int launch_cast<double, double>(hipStream_t, int64_t, const double*, double*);
 
 }  // namespace amgp

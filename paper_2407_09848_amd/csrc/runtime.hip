@@ -1,4 +1,5 @@
 // Host runtime and C ABI: hierarchy setup, smoother dispatch, V-cycle and PCG.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -49,6 +50,9 @@ void free_vecs(Vecs<T>& v, bool own_bx) {
   v = Vecs<T>();
 }
 
+template <typename T>
+void free_adj(std::vector<AdjVecs<T>>& adj);
+
 void drop_graphs(Handle* h) {
   if (h->graphs.empty()) return;
   hipDeviceSynchronize();  // no cached graph may still be executing when it is destroyed
@@ -85,6 +89,12 @@ void release(Handle* h) {
   hipFree(h->cg_q);
   hipFree(h->cg_rold);
   hipFree(h->tmp64);
+  free_adj(h->adj64);
+  free_adj(h->adj32);
+  hipFree(h->tr_buf);
+  hipFree(h->tr_sq);
+  hipFree(h->tr_loss);
+  hipFree(h->tr_partial);
   *h = Handle();
 }
 
@@ -97,8 +107,21 @@ int read_flags(Handle* h, hipStream_t s, int* out) {
 // ---------------------------------------------------------------------------
 // Smoother application on level l in precision T (Sections 2.1-2.2, Algorithm 1).
 // ---------------------------------------------------------------------------
+// Weight descriptor of step j on level l: the per-problem device table when a
+// differentiable V-cycle is running, else none (the launch scalar is used).
+inline Wt step_weight(const Handle* h, int l, int kind, int k, int j) {
+  Wt w;
+  if (kind == AMG_OPTCHEB4 && h->dbeta) {
+    w.v = h->dbeta + (size_t)l * k + (j - 1);
+    w.rpp = (int)(h->lv[l].n / h->nbatch);
+    w.stride = h->nlevels * k;
+  }
+  return w;
+}
+
+// r0_copy (optional, x_in != 0 only): receives r^(0) = b - A x_in, the input of the recurrence.
 template <typename T>
-int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStream_t s) {
+int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStream_t s, T* r0_copy = nullptr) {
   Level& L = h->lv[l];
   const Ell<T>& A = Prec<T>::A(L);
   Vecs<T>& v = Prec<T>::v(L);
@@ -132,28 +155,35 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
     const double c1 = (8.0 * 1 - 4.0) / (2.0 * 1 + 1.0);
     const T* rsrc;
     int j0 = 2;
+    Wt wpend;
     if (xz && k >= 2) {
       // steps 1 and 2 in one pass
       const double alpha2 = (2.0 * 2 - 3.0) / (2.0 * 2 + 1.0), c2 = (8.0 * 2 - 4.0) / (2.0 * 2 + 1.0);
-      AMGP_TRY(launch_first2_zero<T>(s, 0, k > 2, A, minv, b, g[1 - cur], v.r, x, c1, alpha2, c2, w(1), w(2)));
+      AMGP_TRY(launch_first2_zero<T>(s, 0, k > 2, A, minv, b, g[1 - cur], v.r, x, c1, alpha2, c2, w(1), w(2),
+                                     step_weight(h, l, kind, k, 1), step_weight(h, l, kind, k, 2)));
       rsrc = v.r;
       cur = 1 - cur;
       j0 = 3;
     } else if (xz) {
-      AMGP_TRY(launch_first_zero<T>(s, 0, k > 1, n, minv, b, g[cur], nullptr, x, c1, w(1)));
+      AMGP_TRY(launch_first_zero<T>(s, 0, k > 1, n, minv, b, g[cur], nullptr, x, c1, w(1),
+                                    step_weight(h, l, kind, k, 1)));
       rsrc = b;
     } else {
       AMGP_TRY(launch_first_res<T>(s, 0, A, minv, b, x, v.r, g[cur], c1));
+      if (r0_copy) AMGP_TRY(launch_copy<T>(s, n, v.r, r0_copy));
       rsrc = v.r;
       pending = w(1);
-      if (k == 1) return launch_axpy<T>(s, n, pending, g[cur], x);
+      wpend = step_weight(h, l, kind, k, 1);
+      if (k == 1) return launch_axpy<T>(s, n, pending, g[cur], x, wpend);
     }
     for (int j = j0; j <= k; ++j) {
       const double alpha = (2.0 * j - 3.0) / (2.0 * j + 1.0);
       const double c = (8.0 * j - 4.0) / (2.0 * j + 1.0);
-      AMGP_TRY(launch_fused<T>(s, 0, j < k, A, minv, g[cur], g[1 - cur], rsrc, v.r, x, alpha, c, w(j), pending));
+      AMGP_TRY(launch_fused<T>(s, 0, j < k, A, minv, g[cur], g[1 - cur], rsrc, v.r, x, alpha, c, w(j), pending,
+                               step_weight(h, l, kind, k, j), wpend));
       rsrc = v.r;
       pending = 0.0;
+      wpend = Wt();
       cur = 1 - cur;
     }
     return AMG_OK;
@@ -248,6 +278,187 @@ int vcycle_run(Handle* h, int kind, int k, const double* r, double* z, hipStream
   if (ei != hipSuccess) return AMG_EHIP;
   h->graphs.push_back(GraphEntry{kind, k, r, z, exec});
   AMGP_HIP(hipGraphLaunch(exec, s));
+  return AMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Differentiable V-cycle (optimal 4th kind, per-problem per-level weights).
+//
+// Forward: the V-cycle of eq. (amg), saving for every level the input of each
+// smoother recurrence: the level right-hand side b_l (pre-smoothing from 0)
+// and r^(0) = b_l - A_l x_mid (post-smoothing).
+//
+// Backward: every smoother correction Q = sum_j beta_j h_j(M^{-1}A) M^{-1}
+// is symmetric (M diagonal, A symmetric), so the smoother is its own
+// adjoint: for x_out = x_in + Q (b - A x_in),
+//   b_bar += Q x_out_bar,  x_in_bar = x_out_bar - A Q x_out_bar,
+//   d/d beta_j = < z_j(x_out_bar), r^(0) >
+// where z_j(v) is the j-th direction of the recurrence run from zero on v.
+// The transfers are adjoint to each other (P and P^T) and the coarsest solve
+// is symmetric.  A = A^T, so the backward pass reuses the forward SpMV.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TrainPrec;
+template <>
+struct TrainPrec<double> {
+  static AdjVecs<double>& a(Handle* h, int l) { return h->adj64[l]; }
+};
+template <>
+struct TrainPrec<float> {
+  static AdjVecs<float>& a(Handle* h, int l) { return h->adj32[l]; }
+};
+
+template <typename T>
+int alloc_adj(Handle* h, std::vector<AdjVecs<T>>& adj) {
+  adj.resize(h->nlevels);
+  for (int l = 0; l < h->nlevels; ++l) {
+    const int64_t n = h->lv[l].n;
+    AMGP_TRY(dalloc(&adj[l].u, n));
+    AMGP_TRY(dalloc(&adj[l].xmid, n));
+    AMGP_TRY(dalloc(&adj[l].xpre, n));
+    AMGP_TRY(dalloc(&adj[l].res, n));
+    AMGP_TRY(dalloc(&adj[l].xin, n));
+    AMGP_TRY(dalloc(&adj[l].bout, n));
+  }
+  return AMG_OK;
+}
+
+template <typename T>
+void free_adj(std::vector<AdjVecs<T>>& adj) {
+  for (auto& a : adj) {
+    hipFree(a.u);
+    hipFree(a.xmid);
+    hipFree(a.xpre);
+    hipFree(a.res);
+    hipFree(a.xin);
+    hipFree(a.bout);
+  }
+  adj.clear();
+}
+
+int train_prepare(Handle* h) {
+  if (h->train_ready) return AMG_OK;
+  h->ck_off.assign(h->nlevels, 0);
+  int64_t off = 0;
+  for (int l = 0; l < h->nlevels - 1; ++l) {
+    h->ck_off[l] = off;
+    off += 2 * h->lv[l].n;
+  }
+  h->ck_count = off;
+  if (h->precision == AMG_FP32)
+    AMGP_TRY(alloc_adj<float>(h, h->adj32));
+  else
+    AMGP_TRY(alloc_adj<double>(h, h->adj64));
+  const size_t w = h->precision == AMG_FP32 ? sizeof(float) : sizeof(double);
+  const int64_t n0 = h->lv[0].n;
+  // driver: r0, z, r1, r2, g, t (6 x n0) + two checkpoints
+  if (hipMalloc(&h->tr_buf, w * (size_t)(6 * n0 + 2 * std::max<int64_t>(h->ck_count, 1))) != hipSuccess)
+    return AMG_ENOMEM;
+  AMGP_TRY(dalloc(&h->tr_sq, 2 * h->nbatch));
+  AMGP_TRY(dalloc(&h->tr_loss, 1 + h->nbatch));
+  AMGP_TRY(dalloc(&h->tr_partial, 64 * (int64_t)std::max(2 * h->nbatch, 8)));
+  h->train_ready = true;
+  return AMG_OK;
+}
+
+template <typename T>
+int vcycle_fwd_ck(Handle* h, int l, int k, const T* b, T* x, T* ck, hipStream_t s) {
+  if (l == h->nlevels - 1) return coarse<T>(h, b, x, s);
+  Level& L = h->lv[l];
+  Vecs<T>& vc = Prec<T>::v(h->lv[l + 1]);
+  T* ck_pre = ck + h->ck_off[l];
+  T* ck_post = ck_pre + L.n;
+  AMGP_TRY(launch_copy<T>(s, L.n, b, ck_pre));
+  AMGP_TRY(smooth<T>(h, l, AMG_OPTCHEB4, k, b, x, true, s));
+  AMGP_TRY(launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, Prec<T>::v(L).r, vc.b));
+  AMGP_TRY(vcycle_fwd_ck<T>(h, l + 1, k, vc.b, vc.x, ck, s));
+  AMGP_TRY(launch_prolong<T>(s, L.n, L.agg, vc.x, x));
+  return smooth<T>(h, l, AMG_OPTCHEB4, k, b, x, false, s, ck_post);
+}
+
+// u = Q v (smoother from zero on v, every direction z_j kept) and
+// gbeta[p][l][j-1] += < z_j, r0 >_p for every problem p.
+template <typename T>
+int smooth_adjoint(Handle* h, int l, int k, const T* v, T* u, const T* r0, double* gbeta, hipStream_t s) {
+  Level& L = h->lv[l];
+  const Ell<T>& A = Prec<T>::A(L);
+  Vecs<T>& vv = Prec<T>::v(L);
+  const int64_t n = L.n, rpp = n / h->nbatch;
+  const int stride = h->nlevels * k;
+  T* g[2] = {vv.g0, vv.g1};
+  int cur = 0;
+  const double c1 = (8.0 * 1 - 4.0) / (2.0 * 1 + 1.0);
+  AMGP_TRY(launch_first_zero<T>(s, 0, true, n, vv.minv, v, g[cur], nullptr, u, c1, h->beta_at(l, k, 0),
+                                step_weight(h, l, AMG_OPTCHEB4, k, 1)));
+  AMGP_TRY(launch_seg_dot<T>(s, h->nbatch, rpp, g[cur], r0, h->tr_partial, gbeta + (size_t)l * k, stride, true));
+  const T* rsrc = v;
+  for (int j = 2; j <= k; ++j) {
+    const double alpha = (2.0 * j - 3.0) / (2.0 * j + 1.0);
+    const double c = (8.0 * j - 4.0) / (2.0 * j + 1.0);
+    AMGP_TRY(launch_fused<T>(s, 0, true, A, vv.minv, g[cur], g[1 - cur], rsrc, vv.r, u, alpha, c,
+                             h->beta_at(l, k, j - 1), 0.0, step_weight(h, l, AMG_OPTCHEB4, k, j), Wt()));
+    rsrc = vv.r;
+    cur = 1 - cur;
+    AMGP_TRY(launch_seg_dot<T>(s, h->nbatch, rpp, g[cur], r0, h->tr_partial, gbeta + (size_t)l * k + (j - 1),
+                               stride, true));
+  }
+  return AMG_OK;
+}
+
+template <typename T>
+int vcycle_bwd_rec(Handle* h, int l, int k, const T* xo_bar, T* b_bar, const T* ck, double* gbeta, hipStream_t s) {
+  if (l == h->nlevels - 1) return coarse<T>(h, xo_bar, b_bar, s);
+  Level& L = h->lv[l];
+  const Ell<T>& A = Prec<T>::A(L);
+  AdjVecs<T>& a = TrainPrec<T>::a(h, l);
+  AdjVecs<T>& ac = TrainPrec<T>::a(h, l + 1);
+  const T* ck_pre = ck + h->ck_off[l];
+  const T* ck_post = ck_pre + L.n;
+  // post-smoothing: x_out = x_mid + Q (b - A x_mid)
+  AMGP_TRY(smooth_adjoint<T>(h, l, k, xo_bar, a.u, ck_post, gbeta, s));
+  AMGP_TRY(launch_residual<T>(s, A, xo_bar, a.u, a.xmid));  // x_mid_bar = x_out_bar - A u
+  // x_mid = x_pre + P x_c
+  AMGP_TRY(launch_restrict_sum<T>(s, L.nc, L.children, a.xmid, ac.xin));
+  AMGP_TRY(vcycle_bwd_rec<T>(h, l + 1, k, ac.xin, ac.bout, ck, gbeta, s));
+  // b_c = P^T (b - A x_pre)
+  AMGP_TRY(launch_prolong_set<T>(s, L.n, L.agg, ac.bout, a.res));
+  AMGP_TRY(launch_residual<T>(s, A, a.xmid, a.res, a.xpre));  // x_pre_bar = x_mid_bar - A res_bar
+  // pre-smoothing from zero: x_pre = Q b
+  AMGP_TRY(smooth_adjoint<T>(h, l, k, a.xpre, b_bar, ck_pre, gbeta, s));
+  AMGP_TRY(launch_axpy<T>(s, L.n, 1.0, a.u, b_bar));
+  return launch_axpy<T>(s, L.n, 1.0, a.res, b_bar);
+}
+
+template <typename T>
+int train_loss_grad(Handle* h, int k, const double* b, double* hloss, double* gbeta, hipStream_t s) {
+  const int64_t n = h->lv[0].n, rpp = n / h->nbatch;
+  const int P = h->nbatch;
+  const Ell<T>& A = Prec<T>::A(h->lv[0]);
+  T* base = static_cast<T*>(h->tr_buf);
+  T *r0 = base, *z = base + n, *r1 = base + 2 * n, *r2 = base + 3 * n, *g = base + 4 * n, *t = base + 5 * n;
+  T* ckA = base + 6 * n;
+  T* ckB = ckA + h->ck_count;
+  AMGP_TRY((launch_cast<double, T>(s, n, b, r0)));
+  AMGP_TRY(vcycle_fwd_ck<T>(h, 0, k, r0, z, ckA, s));
+  AMGP_TRY(launch_residual<T>(s, A, r0, z, r1));
+  AMGP_TRY(vcycle_fwd_ck<T>(h, 0, k, r1, z, ckB, s));
+  AMGP_TRY(launch_residual<T>(s, A, r1, z, r2));
+  AMGP_TRY(launch_seg_dot<T>(s, P, rpp, r0, nullptr, h->tr_partial, h->tr_sq, 1, false));
+  AMGP_TRY(launch_seg_dot<T>(s, P, rpp, r2, nullptr, h->tr_partial, h->tr_sq + P, 1, false));
+  AMGP_TRY(launch_loss_value(s, P, h->tr_sq, h->tr_loss));
+  AMGP_TRY(launch_loss_seed<T>(s, n, rpp, P, h->tr_sq, r2, g));  // g = dL/dr2
+  AMGP_TRY(launch_fill<double>(s, (int64_t)P * h->nlevels * k, 0.0, gbeta));
+  // r2 = r1 - A z2
+  AMGP_TRY(launch_spmv<T>(s, A, g, t));
+  AMGP_TRY(launch_neg<T>(s, n, t, z));  // z2_bar
+  AMGP_TRY(vcycle_bwd_rec<T>(h, 0, k, z, t, ckB, gbeta, s));  // t = r1_bar through z2
+  AMGP_TRY(launch_axpy<T>(s, n, 1.0, g, t));                 // r1_bar = r2_bar + ...
+  // r1 = r0 - A z1
+  AMGP_TRY(launch_spmv<T>(s, A, t, g));
+  AMGP_TRY(launch_neg<T>(s, n, g, z));  // z1_bar
+  AMGP_TRY(vcycle_bwd_rec<T>(h, 0, k, z, t, ckA, gbeta, s));
+  AMGP_HIP(hipMemcpyAsync(hloss, h->tr_loss, sizeof(double) * (1 + P), hipMemcpyDeviceToHost, s));
+  AMGP_HIP(hipStreamSynchronize(s));
   return AMG_OK;
 }
 
@@ -599,6 +810,161 @@ int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_
   AMGP_TRY(amgp::check_kind_degree(kind, degree));
   return amgp::pcg(&h->impl, kind, degree, d_b, d_x, x_is_zero != 0, rtol, maxit, flexible != 0, h_iters, h_relres,
                    h_hist, (hipStream_t)stream);
+}
+
+int amg_ckpt_bytes(const amg_handle* h, int64_t* h_bytes) {
+  if (!h || !h_bytes) return AMG_EINVAL;
+  Handle* H = const_cast<Handle*>(&h->impl);
+  AMGP_TRY(amgp::train_prepare(H));
+  *h_bytes = H->ck_count * (int64_t)(H->precision == AMG_FP32 ? sizeof(float) : sizeof(double));
+  return AMG_OK;
+}
+
+namespace {
+struct DbetaScope {  // installs the per-problem weight table for the duration of one call
+  Handle* h;
+  DbetaScope(Handle* hh, const double* b, int k) : h(hh) {
+    h->dbeta = b;
+    h->dbeta_k = k;
+  }
+  ~DbetaScope() {
+    h->dbeta = nullptr;
+    h->dbeta_k = 0;
+  }
+};
+}  // namespace
+
+int vcycle_fwd_ckpt(amg_handle* h, int degree, const double* d_beta, const double* d_r, double* d_z, void* d_ckpt,
+                    void* stream) {
+  if (!h || !d_beta || !d_r || !d_z || !d_ckpt || degree < 1 || degree > AMG_MAX_DEGREE) return AMG_EINVAL;
+  Handle* H = &h->impl;
+  hipStream_t s = (hipStream_t)stream;
+  AMGP_TRY(amgp::train_prepare(H));
+  DbetaScope scope(H, d_beta, degree);
+  if (H->precision == AMG_FP32) {
+    amgp::Vecs<float>& v = H->lv[0].v32;
+    AMGP_TRY((amgp::launch_cast<double, float>(s, H->lv[0].n, d_r, v.b)));
+    AMGP_TRY(amgp::vcycle_fwd_ck<float>(H, 0, degree, v.b, v.x, static_cast<float*>(d_ckpt), s));
+    return amgp::launch_cast<float, double>(s, H->lv[0].n, v.x, d_z);
+  }
+  return amgp::vcycle_fwd_ck<double>(H, 0, degree, d_r, d_z, static_cast<double*>(d_ckpt), s);
+}
+
+int vcycle_bwd(amg_handle* h, int degree, const double* d_beta, const void* d_ckpt, const double* d_gz,
+               double* d_gr, double* d_gbeta, void* stream) {
+  if (!h || !d_beta || !d_ckpt || !d_gz || !d_gr || !d_gbeta || degree < 1 || degree > AMG_MAX_DEGREE)
+    return AMG_EINVAL;
+  Handle* H = &h->impl;
+  hipStream_t s = (hipStream_t)stream;
+  AMGP_TRY(amgp::train_prepare(H));
+  DbetaScope scope(H, d_beta, degree);
+  if (H->precision == AMG_FP32) {
+    amgp::AdjVecs<float>& a = H->adj32[0];
+    AMGP_TRY((amgp::launch_cast<double, float>(s, H->lv[0].n, d_gz, a.xin)));
+    AMGP_TRY(amgp::vcycle_bwd_rec<float>(H, 0, degree, a.xin, a.bout, static_cast<const float*>(d_ckpt), d_gbeta, s));
+    return amgp::launch_cast<float, double>(s, H->lv[0].n, a.bout, d_gr);
+  }
+  return amgp::vcycle_bwd_rec<double>(H, 0, degree, d_gz, d_gr, static_cast<const double*>(d_ckpt), d_gbeta, s);
+}
+
+int amg_train_loss_grad(amg_handle* h, int degree, const double* d_beta, const double* d_b, double* h_loss,
+                        double* d_gbeta, void* stream) {
+  if (!h || !d_beta || !d_b || !h_loss || !d_gbeta || degree < 1 || degree > AMG_MAX_DEGREE) return AMG_EINVAL;
+  Handle* H = &h->impl;
+  if (H->nlevels < 2) return AMG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  AMGP_TRY(amgp::train_prepare(H));
+  DbetaScope scope(H, d_beta, degree);
+  if (H->precision == AMG_FP32) return amgp::train_loss_grad<float>(H, degree, d_b, h_loss, d_gbeta, s);
+  return amgp::train_loss_grad<double>(H, degree, d_b, h_loss, d_gbeta, s);
+}
+
+int amg_level_features(amg_handle* h, int degree, const double* h_sigma, float* d_feat, void* stream) {
+  if (!h || !h_sigma || !d_feat || degree < 1 || degree > AMG_MAX_DEGREE) return AMG_EINVAL;
+  Handle* H = &h->impl;
+  if (H->nlevels < 2) return AMG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int P = H->nbatch, NL = H->nlevels - 1;
+  std::vector<float> feat((size_t)P * NL * 8);
+  double* buf = nullptr;
+  double* red = nullptr;
+  double* part = nullptr;
+  const int64_t n0 = H->lv[0].n;
+  if (hipMalloc(&buf, sizeof(double) * 3 * n0) != hipSuccess) return AMG_ENOMEM;
+  if (hipMalloc(&red, sizeof(double) * 3 * P) != hipSuccess) return AMG_ENOMEM;
+  if (hipMalloc(&part, sizeof(double) * 64 * P) != hipSuccess) return AMG_ENOMEM;
+  int rc = AMG_OK;
+  std::vector<double> hr(3 * P);
+  for (int l = 0; l < NL && rc == AMG_OK; ++l) {
+    amgp::Level& L = H->lv[l];
+    const int64_t n = L.n, rpp = n / P;
+    double *v = buf, *w = buf + n, *t = buf + 2 * n;
+    // 20 power iterations on M^{-1} A from the all-ones vector: lambda ~ ||v_20|| / ||v_19|| per problem
+    rc = amgp::launch_fill<double>(s, n, 1.0, v);
+    for (int it = 0; it < 20 && rc == AMG_OK; ++it) {
+      rc = amgp::launch_spmv<double>(s, L.A64, v, t);
+      if (rc == AMG_OK) rc = amgp::launch_mul(s, n, L.v64.minv, t, w);
+      std::swap(v, w);
+    }
+    if (rc == AMG_OK) rc = amgp::launch_seg_dot<double>(s, P, rpp, v, nullptr, part, red, 1, false);
+    if (rc == AMG_OK) rc = amgp::launch_seg_dot<double>(s, P, rpp, w, nullptr, part, red + P, 1, false);
+    // mean off-diagonal l1 ratio: plain per-problem sum = dot with a vector of ones
+    if (rc == AMG_OK) rc = amgp::launch_offdiag_ratio(s, n, L.csr_ptr, L.csr_col, L.csr_val, L.v64.minv, t);
+    if (rc == AMG_OK) rc = amgp::launch_fill<double>(s, n, 1.0, w);
+    if (rc == AMG_OK) rc = amgp::launch_seg_dot<double>(s, P, rpp, t, w, part, red + 2 * P, 1, false);
+    if (rc != AMG_OK) break;
+    if (hipMemcpyAsync(hr.data(), red, sizeof(double) * 3 * P, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = AMG_EHIP;
+      break;
+    }
+    const double nnz_per_row = (double)L.nnz / (double)n;
+    const double ratio_next = (double)H->lv[l + 1].n / (double)n;
+    for (int p = 0; p < P; ++p) {
+      const double lam = hr[P + p] > 0.0 ? std::sqrt(hr[p] / hr[P + p]) : 0.0;
+      float* f = &feat[((size_t)p * NL + l) * 8];
+      f[0] = (float)(degree / 6.0);
+      f[1] = (float)((double)l / (double)(H->nlevels - 1));
+      f[2] = (float)(1.0 - lam);
+      f[3] = (float)(nnz_per_row / 27.0);
+      f[4] = (float)(std::log2((double)rpp) / 24.0);
+      f[5] = (float)h_sigma[p];
+      f[6] = (float)ratio_next;
+      f[7] = (float)(hr[2 * P + p] / (double)rpp);
+    }
+  }
+  if (rc == AMG_OK && hipMemcpyAsync(d_feat, feat.data(), sizeof(float) * feat.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = AMG_EHIP;
+  hipStreamSynchronize(s);
+  hipFree(buf);
+  hipFree(red);
+  hipFree(part);
+  return rc;
+}
+
+int mlp_num_params(void) { return amgp::mlp_num_params(); }
+
+int mlp_fwd(const float* d_params, const float* d_x, int batch, float* d_y, float* d_cache, void* stream) {
+  if (!d_params || !d_x || !d_y || !d_cache || batch < 1 || batch > 256) return AMG_EINVAL;
+  return amgp::launch_mlp_fwd((hipStream_t)stream, batch, d_params, d_x, d_y, d_cache);
+}
+
+int mlp_bwd(const float* d_params, const float* d_x, int batch, const float* d_cache, const float* d_gy,
+            float* d_gparams, float* d_work, void* stream) {
+  if (!d_params || !d_x || !d_cache || !d_gy || !d_gparams || !d_work || batch < 1 || batch > 256) return AMG_EINVAL;
+  return amgp::launch_mlp_bwd((hipStream_t)stream, batch, d_params, d_x, d_cache, d_gy, d_gparams, d_work);
+}
+
+int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, int step, float lr, float b1, float b2,
+             float eps, void* stream) {
+  if (!d_params || !d_g || !d_m || !d_v || n < 1 || step < 1) return AMG_EINVAL;
+  const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+  return amgp::launch_adam((hipStream_t)stream, n, d_params, d_g, d_m, d_v, lr, b1, b2, eps, c1, c2);
+}
+
+int amg_beta_valid(const double* d_beta, int count, int degree, int ngrid, int* d_valid, void* stream) {
+  if (!d_beta || !d_valid || count < 1 || degree < 1 || degree > AMG_MAX_DEGREE || ngrid < 1) return AMG_EINVAL;
+  return amgp::launch_beta_valid((hipStream_t)stream, count, degree, d_beta, ngrid, d_valid);
 }
 
 const char* amg_strerror(int code) {

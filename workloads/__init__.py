@@ -33,6 +33,8 @@ __all__ = [
     "SEED_RHS",
     "SEED_GRF",
     "SEED_MLP",
+    "mlp_init",
+    "config4_sigmas",
 ]
 
 # Seed bases: b uses default_rng(SEED_RHS + config number), the Gaussian
@@ -283,3 +285,24 @@ def config_problem(cfg: int, size: int | None = None):
         raise ValueError(cfg)
     b = rhs_uniform(A.n, SEED_RHS + cfg)
     return A, b, meta
+
+
+def config4_sigmas(nprob=32):
+    """sigma of stacked problem p in the learned-weights workload: cycles over (0.5, 1, 2)."""
+    return [(0.5, 1.0, 2.0)[p % 3] for p in range(nprob)]
+
+
+def mlp_init(seed: int = SEED_MLP):
+    """Initial parameters of the 8-64-64-6 network, float64 vector of 5126 entries laid out as
+    W1[64][8], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]: weights ~ U(-1/sqrt(fan_in),
+    1/sqrt(fan_in)) drawn in that order from default_rng(seed), biases 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, is_w in (((64, 8), True), ((64,), False), ((64, 64), True), ((64,), False),
+                        ((6, 64), True), ((6,), False)):
+        if is_w:
+            bound = 1.0 / np.sqrt(shape[1])
+            parts.append(rng.uniform(-bound, bound, shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts)
