@@ -69,16 +69,21 @@ def vcycle_bytes(levels, ncp, nbatch, kind, k, w=8):
         tot += b_first_res(nnz, n, w) + max(k - 2, 0) * b_fused(nnz, n, True, w) + \
             (b_fused(nnz, n, False, w) if k > 1 else 2 * w * n + w * n)
     nL = levels[-1][0]
-    tot += nbatch * ncp * ncp * 8 + 2 * 8 * nbatch * ncp + 2 * w * nL
+    nb = ncp // 64
+    # coarsest: the lower 64x64 blocks of the symmetric inverse once, the block partials written and read
+    tot += nbatch * (nb * (nb + 1) // 2) * 64 * 64 * 8 + 2 * nbatch * nb * nb * 64 * 8 + 2 * w * nL
     return tot
 
 
 def pcg_bytes(levels, ncp, nbatch, kind, k, iters, w=8):
     n, nnz = levels[0]
-    per_it = (12 * nnz + 16 * n) + 48 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 24 * n
+    # SpMV with the fused direction update (gathers z and p_old, writes p and q), x/r update with (r, r),
+    # the V-cycle, and (r, z)
+    per_it = (12 * nnz + 32 * n) + 48 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n
     if w == 4:
         per_it += 12 * n  # casts r -> f32, z -> f64
-    setup = 16 * n + 16 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 16 * n
+    # x = 0, r = b, the first V-cycle, (r, z), p_old = 0
+    setup = 8 * n + 16 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 8 * n
     return setup + iters * per_it
 
 
@@ -102,6 +107,87 @@ def measured_traffic(size):
         return None
 
 
+def stacked_diffusion(W, nprob, size, seed0):
+    import numpy as np
+    sig = W.config4_sigmas(nprob)
+    mats = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((size, size, size), 8.0, seed0 + p)))
+            for p in range(nprob)]
+    return W.stack_block_diagonal(mats), sig
+
+
+def learned_variant(args, amg, W, h, bd, x, stream, variants):
+    """Train the 8-64-64-6 network on 32 stacked 64^3 diffusion problems (the learned-weights
+    workload, FP32, the library's adjoint and network kernels), report its loss against the plain
+    optimal weights at degree 6 and at the bench degree, then apply the bench-degree network to
+    this system (kept only if it lowers the two-cycle residual ratio here) and time the solve."""
+    import numpy as np
+    import torch
+
+    from paper_2407_09848_amd import learned
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = {}
+    t0 = time.perf_counter()
+    big, sig = stacked_diffusion(W, 32, 64, W.SEED_GRF)
+    held, _ = stacked_diffusion(W, 32, 64, W.SEED_GRF + 500)
+    b4 = dev(W.rhs_uniform(big.n, W.SEED_RHS + 4))
+    b4h = dev(W.rhs_uniform(held.n, W.SEED_RHS + 40))
+    hs = [amg.amg_setup(dev(M.row_ptr), dev(M.col), dev(M.val), M.grid[0], M.grid[1], M.grid[2] // 32, 32,
+                        4096, amg.AMG_FP32) for M in (big, held)]
+    out["setup_s"] = round(time.perf_counter() - t0, 2)
+    nets = {}
+    for deg in sorted({6, args.degree}):
+        t0 = time.perf_counter()
+        res = learned.train(hs[0], b4, sig, degree=deg, steps=args.train_steps, lr=3e-3,
+                            init_params=W.mlp_init(W.SEED_MLP))
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        f = amg.amg_level_features(hs[0], deg, sig)
+        beta, _, valid = learned.predict_beta(hs[0], res.params, f, deg, 32)
+        lt, _ = learned.evaluate(hs[0], beta, b4, deg, 32)
+        fh = amg.amg_level_features(hs[1], deg, sig)
+        bh, _, _ = learned.predict_beta(hs[1], res.params, fh, deg, 32)
+        L = amg.amg_num_levels(hs[1])
+        plain = dev(np.tile(np.array(amg.amg_default_beta(deg)), (32, L, 1)).ravel())
+        lh, _ = learned.evaluate(hs[1], bh, b4h, deg, 32)
+        lp, _ = learned.evaluate(hs[1], plain, b4h, deg, 32)
+        out[f"degree{deg}"] = {"train_steps": args.train_steps, "train_s": round(tt, 2),
+                               "train_loss_plain": round(res.plain_loss, 6), "train_loss_learned": round(lt, 6),
+                               "heldout_loss_plain": round(lp, 6), "heldout_loss_learned": round(lh, 6),
+                               "invalid_rows": int((valid == 0).sum().item())}
+        nets[deg] = res.params
+    for hh in hs:
+        amg.amg_destroy(hh)
+    # apply to this system at the bench degree, judged by the two-cycle residual ratio here
+    deg = args.degree
+    lb = learned.learned_level_betas(h, nets[deg], deg, 0.0)
+    L = amg.amg_num_levels(h)
+    tab_l = np.array(amg.amg_default_beta(deg) * L).reshape(L, deg)
+    tab_l[:L - 1] = np.array(lb)
+    plain = dev(np.tile(np.array(amg.amg_default_beta(deg)), (L, 1)).ravel())
+    r_learned, _ = learned.evaluate(h, dev(tab_l.ravel()), bd, deg, 1)
+    r_plain, _ = learned.evaluate(h, plain, bd, deg, 1)
+    use = r_learned < r_plain
+    if use:
+        learned.apply_level_betas(h, deg, lb)
+    amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        rc, itv, relv, _ = amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    amg.amg_reset_beta(h)
+    tm = e0.elapsed_time(e1) / 3
+    base = variants.get(f"fp64_optcheb4_k{deg}", {}).get("ms")
+    variants[f"learned_optcheb4_k{deg}"] = {"ms": round(tm, 3), "iters": itv,
+                                           "vs_plain_fp64": round(tm / base, 3) if base else None,
+                                           "weights": "learned" if use else "plain (fallback)"}
+    out["this_system"] = {"two_cycle_ratio_plain": round(r_plain, 6), "two_cycle_ratio_learned": round(r_learned, 6),
+                          "weights_used": "learned" if use else "plain (fallback)", "level_betas": lb}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +198,8 @@ def main():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip training the learned-weight network")
+    ap.add_argument("--train-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
@@ -226,6 +314,10 @@ def main():
         base = variants[f"fp64_{names[args.kind]}_k{args.degree}"]["ms"]
         for v in variants.values():
             v["vs_plain_fp64"] = round(v["ms"] / base, 3)
+    # ---- learned weights: trained on the stacked diffusion problems, applied to this system ----
+    learned_info = None
+    if not args.no_variants and not args.no_learned:
+        learned_info = learned_variant(args, amg, W, h, bd, x, stream, variants)
     amg.amg_destroy(h)
 
     # ---- CPU baseline: the oracle solving the same system once ----
@@ -254,7 +346,7 @@ def main():
                    "smoother": {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}[args.kind],
                    "degree": args.degree, "n": int(n0), "nnz": int(nnz0), "levels": [int(l[0]) for l in levels],
                    "iters": it, "setup_s": round(setup_s, 3)},
-        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants, "learned": learned_info,
     }
     print(json.dumps(out), flush=True)
 

@@ -120,6 +120,7 @@ struct Handle {
   double* ainv = nullptr;  // [nbatch][ncp][ncp]
   double* cb = nullptr;    // [nbatch * ncp] padded coarse rhs
   double* cx = nullptr;    // [nbatch * ncp] padded coarse solution
+  double* cpart = nullptr; // [nbatch][ncp/64][ncp/64][64] partial products of the blocked symmetric solve
   // beta weights: [level][degree][j]
   std::vector<double> beta;  // size nlevels * (AMG_MAX_DEGREE+1) * AMG_MAX_DEGREE
   // reductions and CG workspace (fine level, float64)
@@ -127,7 +128,7 @@ struct Handle {
   double* scal = nullptr;     // device scalars
   double* hscal = nullptr;    // pinned host mirror
   int* dflag = nullptr;       // device error flags
-  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_rold = nullptr;
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr, *cg_q = nullptr, *cg_rold = nullptr;
   double *tmp64 = nullptr;    // level-0 scratch (n0)
   double& beta_at(int l, int k, int j) {
     return beta[((size_t)l * (AMG_MAX_DEGREE + 1) + k) * AMG_MAX_DEGREE + j];
@@ -206,6 +207,9 @@ int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, cons
                 double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
 int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
                     unsigned* nblocks);
+// p_new = z + beta p_old (beta from scal), q = A p_new, partials of (p_new, q)
+int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
+                      double* pnew, double* q, double* partial, unsigned* nblocks);
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks);
 int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p);
@@ -260,5 +264,9 @@ void free_ell(Ell<float>& e);
 // In place: dense[nbatch][np][np] (SPD, lower part used) -> inverse A^{-1}, full symmetric.
 int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np, double* dense, int* flag);
 int launch_coarse_gemv(hipStream_t s, int nbatch, int64_t np, const double* ainv, const double* b, double* x);
+// x = A^{-1} b from the lower blocks of the symmetric inverse; part holds nbatch * (np/64)^2 * 64 doubles
+template <typename T>
+int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,
+                       double* part);
 
 }  // namespace amgp

@@ -175,6 +175,52 @@ __global__ __launch_bounds__(256) void k_gemv(int np, const double* __restrict__
   if (lane == 0) x[(long long)p * np + row] = acc;
 }
 
+// x = A^{-1} b for the symmetric dense inverse, reading only its lower 64x64
+// blocks, each exactly once.  Block (J, I), J >= I, of problem p is handled
+// by one wavefront: it contributes A_JI b_I to rows of block J and, when
+// J > I, A_JI^T b_J to rows of block I.  The 64-vectors land in
+// part[p][row block][column block]; a second kernel sums them in a fixed order.
+// b and x are level vectors (nl rows per problem); padding rows read as 0.
+template <typename T>
+__global__ __launch_bounds__(64) void k_symv_blocks(int nb, int64_t nl, int64_t np, const double* __restrict__ Ainv,
+                                                    const T* __restrict__ b, double* __restrict__ part) {
+  __shared__ double tile[TM][TM + 1];
+  __shared__ double bi[TM], bj[TM];
+  const int p = blockIdx.y;
+  // map the linear block index to (J, I) with J >= I: q = J (J + 1) / 2 + I
+  const int q = blockIdx.x;
+  int J = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= q) ++J;
+  while (J * (J + 1) / 2 > q) --J;
+  const int I = q - J * (J + 1) / 2;
+  const int t = threadIdx.x;
+  const double* A = Ainv + (int64_t)p * np * np;
+  const T* bp = b + (int64_t)p * nl;
+  const int64_t ri = (int64_t)I * TM + t, rj = (int64_t)J * TM + t;
+  bi[t] = ri < nl ? (double)bp[ri] : 0.0;
+  bj[t] = rj < nl ? (double)bp[rj] : 0.0;
+  for (int a = 0; a < TM; ++a) tile[a][t] = A[((int64_t)J * TM + a) * np + (int64_t)I * TM + t];
+  __syncthreads();
+  double row = 0.0, colsum = 0.0;
+  for (int c = 0; c < TM; ++c) row += tile[t][c] * bi[c];  // (A_JI b_I)_t
+  double* out = part + (int64_t)p * nb * nb * TM;
+  out[((int64_t)J * nb + I) * TM + t] = row;
+  if (J > I) {
+    for (int a = 0; a < TM; ++a) colsum += tile[a][t] * bj[a];  // (A_JI^T b_J)_t
+    out[((int64_t)I * nb + J) * TM + t] = colsum;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TM) void k_symv_sum(int nb, int64_t nl, const double* __restrict__ part, T* __restrict__ x) {
+  const int p = blockIdx.y, I = blockIdx.x, t = threadIdx.x;
+  const int64_t row = (int64_t)I * TM + t;
+  const double* in = part + (int64_t)p * nb * nb * TM + (int64_t)I * nb * TM;
+  double s = 0.0;
+  for (int J = 0; J < nb; ++J) s += in[(int64_t)J * TM + t];
+  if (row < nl) x[(int64_t)p * nl + row] = (T)s;
+}
+
 template <bool TA, bool TB>
 int gemm(hipStream_t s, int batch, int M, int N, int K, double alpha, const double* A, int lda, long long sA,
          const double* B, int ldb, long long sB, double beta, double* C, int ldc, long long sC) {
@@ -243,6 +289,19 @@ int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np64, double* dense, in
   hipFree(T);
   return AMG_OK;
 }
+
+template <typename T>
+int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,
+                       double* part) {
+  const int nb = (int)(np / TM);
+  hipLaunchKernelGGL(k_symv_blocks<T>, dim3(nb * (nb + 1) / 2, nbatch), dim3(TM), 0, s, nb, nl, np, ainv, b, part);
+  hipLaunchKernelGGL(k_symv_sum<T>, dim3(nb, nbatch), dim3(TM), 0, s, nb, nl, (const double*)part, x);
+  return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
+}
+template int launch_coarse_symv<double>(hipStream_t, int, int64_t, int64_t, const double*, const double*, double*,
+                                        double*);
+template int launch_coarse_symv<float>(hipStream_t, int, int64_t, int64_t, const double*, const float*, float*,
+                                       double*);
 
 int launch_coarse_gemv(hipStream_t s, int nbatch, int64_t np, const double* ainv, const double* b, double* x) {
   dim3 grid((unsigned)((np + 3) / 4), nbatch);

@@ -349,6 +349,36 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> 
   if (threadIdx.x == 0) partial[logical_block()] = s;
 }
 
+// The CG direction update fused into the next SpMV: p_new = z + beta p_old and
+// q = A p_new, with (p_new, q) partials.  p_new of a neighbour is formed on the
+// fly from z and p_old (exactly the value stored for it), so p_new is written
+// to the other buffer of a pair.
+__global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double> A, const double* __restrict__ scal,
+                                                       const double* __restrict__ z, const double* __restrict__ pold,
+                                                       double* __restrict__ pnew, double* __restrict__ q,
+                                                       double* __restrict__ partial) {
+  const int64_t i = row_index();
+  const double beta = scal[S_BETA];
+  double v = 0.0;
+  if (i < n) {
+    const int s = __builtin_amdgcn_readfirstlane((int)(i >> 6));
+    const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
+    const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
+    double acc = 0.0;
+#pragma unroll 4
+    for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
+      const int j = A.col[p];
+      acc += A.val[p] * (z[j] + beta * pold[j]);
+    }
+    const double pi = z[i] + beta * pold[i];
+    pnew[i] = pi;
+    q[i] = acc;
+    v = pi * acc;
+  }
+  const double sum = block_sum(v);
+  if (threadIdx.x == 0) partial[logical_block()] = sum;
+}
+
 // x += alpha p, r -= alpha q (alpha from the device scalars), partial (r, r);
 // rold (flexible CG) receives the previous r.
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ scal,
@@ -406,6 +436,7 @@ __global__ __launch_bounds__(1024) void k_reduce(int mode, unsigned nb, const do
       break;
     case RED_RZ0:
       scal[S_RZ] = s;
+      scal[S_BETA] = 0.0;
       break;
     case RED_ALPHA:
       scal[S_PQ] = s;
@@ -589,6 +620,14 @@ int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double
                     unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
   hipLaunchKernelGGL(k_spmv_dot, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
+  *nblocks = g;
+  return LAUNCH_OK();
+}
+
+int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
+                      double* pnew, double* q, double* partial, unsigned* nblocks) {
+  const unsigned g = xcd_grid(A.n);
+  hipLaunchKernelGGL(k_spmv_dot_p, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q, partial);
   *nblocks = g;
   return LAUNCH_OK();
 }

@@ -79,6 +79,7 @@ void release(Handle* h) {
   hipFree(h->ainv);
   hipFree(h->cb);
   hipFree(h->cx);
+  hipFree(h->cpart);
   hipFree(h->partial);
   hipFree(h->scal);
   hipFree(h->dflag);
@@ -86,6 +87,7 @@ void release(Handle* h) {
   hipFree(h->cg_r);
   hipFree(h->cg_z);
   hipFree(h->cg_p);
+  hipFree(h->cg_p2);
   hipFree(h->cg_q);
   hipFree(h->cg_rold);
   hipFree(h->tmp64);
@@ -222,9 +224,7 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
 
 template <typename T>
 int coarse(Handle* h, const T* b, T* x, hipStream_t s) {
-  AMGP_TRY(launch_pad_in<T>(s, h->nbatch, h->ncl, h->ncp, b, h->cb));
-  AMGP_TRY(launch_coarse_gemv(s, h->nbatch, h->ncp, h->ainv, h->cb, h->cx));
-  return launch_pad_out<T>(s, h->nbatch, h->ncl, h->ncp, h->cx, x);
+  return launch_coarse_symv<T>(s, h->nbatch, h->ncl, h->ncp, h->ainv, b, x, h->cpart);
 }
 
 // V-cycle of eq. (amg) from level l: x = B_l b.
@@ -549,6 +549,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     AMGP_TRY(dalloc(&h->ainv, (int64_t)h->nbatch * h->ncp * h->ncp));
     AMGP_TRY(dalloc(&h->cb, (int64_t)h->nbatch * h->ncp));
     AMGP_TRY(dalloc(&h->cx, (int64_t)h->nbatch * h->ncp));
+    AMGP_TRY(dalloc(&h->cpart, (int64_t)h->nbatch * (h->ncp / kDenseTile) * (h->ncp / kDenseTile) * kDenseTile));
     AMGP_TRY(launch_to_dense(s, h->nbatch, h->ncl, h->ncp, L.csr_ptr, L.csr_col, L.csr_val, h->ainv, h->dflag));
     AMGP_TRY(dense_spd_inverse(s, h->nbatch, h->ncp, h->ainv, h->dflag));
     int fl[F_NFLAG];
@@ -576,6 +577,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   AMGP_TRY(dalloc(&h->cg_r, n0));
   AMGP_TRY(dalloc(&h->cg_z, n0));
   AMGP_TRY(dalloc(&h->cg_p, n0));
+  AMGP_TRY(dalloc(&h->cg_p2, n0));
   AMGP_TRY(dalloc(&h->cg_q, n0));
   AMGP_TRY(dalloc(&h->cg_rold, n0));
   AMGP_TRY(dalloc(&h->tmp64, n0));
@@ -636,11 +638,12 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   *relres = rel0;
   if (rel0 <= rtol) return AMG_OK;
   AMGP_TRY(vcycle_run(h, kind, k, r, z, s));
-  AMGP_TRY(sum_dot(h, s, RED_RZ0, r, z, nullptr, nullptr, n));
-  AMGP_TRY(launch_copy<double>(s, n, z, p));
+  AMGP_TRY(sum_dot(h, s, RED_RZ0, r, z, nullptr, nullptr, n));  // also sets beta = 0: p_1 = z_0
+  double* pold = h->cg_p2;
+  AMGP_TRY(launch_fill<double>(s, n, 0.0, pold));
   for (int it = 1; it <= maxit; ++it) {
     unsigned nb = 0;
-    AMGP_TRY(launch_spmv_dot(s, A, p, q, h->partial, &nb));
+    AMGP_TRY(launch_spmv_dot_p(s, A, h->scal, z, pold, p, q, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_ALPHA, nb, h->partial, h->scal, h->dflag));
     AMGP_TRY(launch_cg_update(s, n, h->scal, p, q, x, r, rold, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag));
@@ -658,7 +661,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
       AMGP_TRY(sum_dot(h, s, RED_BETA_FLEX, r, z, rold, z, n));
     else
       AMGP_TRY(sum_dot(h, s, RED_BETA, r, z, nullptr, nullptr, n));
-    AMGP_TRY(launch_cg_pupdate(s, n, h->scal, z, p));
+    std::swap(p, pold);  // the next iteration forms p = z + beta pold inside its SpMV
   }
   return AMG_NOT_CONVERGED;
 }

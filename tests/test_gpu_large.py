@@ -1,0 +1,153 @@
+"""Full-size checks (GPU): the 27-point Q1 Laplacian at 320^3 (32.8M rows, 879M stored entries)
+and the FV diffusion problem at 256^3.
+
+At these sizes the oracle cannot run a whole solve in a test, so:
+* smoother outputs are checked on sampled rows: after k steps from x = 0 the
+  value at row i depends only on rows within grid distance k of i, so the
+  oracle recurrence on the radius-k sub-grid around i (with M^{-1} taken from
+  the full rows) reproduces it exactly;
+* CG solutions are checked through properties that hold at any size: the
+  true residual ||b - A x|| / ||b|| computed by the oracle's SpMV, and the
+  FP32-hierarchy solve against the FP64 one.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_util import dev, hierarchy, host, nan_vec, oracle_params, torch_cuda  # noqa: E402
+
+import workloads as W  # noqa: E402
+from oracle import smoothers as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    torch_cuda()
+    t = time.time()
+    A, b, _ = W.config_problem(5)
+    _log(f"C5 assembled: n={A.n} nnz={A.nnz} in {time.time() - t:.0f} s")
+    return A, b, A.to_scipy()
+
+
+def _l1_rows(As, rows):
+    """M^{-1} of the given global rows, from their full rows."""
+    sub = As[rows]
+    grow = np.repeat(rows, np.diff(sub.indptr))
+    diag = sub.indices == grow
+    M = np.zeros(rows.size)
+    lr = np.repeat(np.arange(rows.size), np.diff(sub.indptr))
+    np.add.at(M, lr[diag], sub.data[diag])
+    np.add.at(M, lr[~diag], np.abs(sub.data[~diag]))
+    return 1.0 / M
+
+
+def _sample_rows(nx, rng, count):
+    pts = [(0, 0, 0), (nx - 1, nx - 1, nx - 1), (0, nx // 2, nx - 1), (nx // 2, nx // 2, nx // 2), (1, 2, 3)]
+    while len(pts) < count:
+        pts.append(tuple(int(v) for v in rng.integers(0, nx, 3)))
+    return pts
+
+
+def _local_value(As, Minv_full, b, grid, pt, kind, k, R):
+    nx, ny, nz = grid
+    i0, j0, k0 = pt
+    ii = np.arange(max(0, i0 - R), min(nx, i0 + R + 1))
+    jj = np.arange(max(0, j0 - R), min(ny, j0 + R + 1))
+    kk = np.arange(max(0, k0 - R), min(nz, k0 + R + 1))
+    rows = (ii[None, None, :] + nx * jj[None, :, None] + nx * ny * kk[:, None, None]).ravel()
+    sub = As[rows][:, rows]
+    beta, a = oracle_params(kind, k)
+    x = S.smooth(sub, Minv_full[rows], b[rows], None, kind, k, beta, a)
+    centre = int(np.where(rows == i0 + nx * j0 + nx * ny * k0)[0][0])
+    return x[centre]
+
+
+def test_c5_smoother_sampled_rows(c5):
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    A, b, As = c5
+    rng = np.random.default_rng(11)
+    pts = _sample_rows(A.grid[0], rng, 40)
+    idx = np.array([p[0] + A.grid[0] * p[1] + A.grid[0] * A.grid[1] * p[2] for p in pts])
+    k = 4
+    need = set()
+    for (i0, j0, k0) in pts:
+        for dk in range(-k, k + 1):
+            for dj in range(-k, k + 1):
+                for di in range(-k, k + 1):
+                    i, j, kz = i0 + di, j0 + dj, k0 + dk
+                    if 0 <= i < A.grid[0] and 0 <= j < A.grid[1] and 0 <= kz < A.grid[2]:
+                        need.add(i + A.grid[0] * j + A.grid[0] * A.grid[1] * kz)
+    need = np.array(sorted(need))
+    Minv = np.zeros(A.n)
+    Minv[need] = _l1_rows(As, need)
+    with hierarchy(A) as h:
+        _log(f"C5 levels {[amg.amg_level_info(h, l)[0] for l in range(amg.amg_num_levels(h))]}")
+        bd = dev(b)
+        for kind in (2, 3):
+            x = nan_vec(A.n)
+            amg.smoother_apply(h, 0, kind, k, bd, x, True)
+            torch.cuda.synchronize()
+            xh = host(x)
+            assert np.all(np.isfinite(xh))
+            for pt, xv in zip(pts, xh[idx]):
+                xo = _local_value(As, Minv, b, A.grid, pt, kind, k, k)
+                assert abs(xv - xo) <= 1e-12 * max(abs(xo), 1e-3), (kind, pt, xv, xo)
+            _log(f"kind {kind}: {len(pts)} sampled rows match the oracle")
+
+
+def test_c5_pcg_variants(c5):
+    """AMG-PCG to 1e-8 on 320^3: plain FP64 optimal 4th kind, FP32 hierarchy, optimal 1st kind (k = 4);
+    the true residual of each solution is checked with the oracle's SpMV."""
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    A, b, As = c5
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    for prec in (amg.AMG_FP64, amg.AMG_FP32):
+        with hierarchy(A, precision=prec) as h:
+            L = amg.amg_num_levels(h)
+            assert L == 6 and amg.amg_level_info(h, L - 1)[0] == 1000
+            for kind in ((2, 3) if prec == amg.AMG_FP64 else (2,)):
+                x = nan_vec(A.n)
+                t = time.time()
+                rc, it, rel, _ = amg.pcg_solve(h, kind, 4, bd, x, True, 1e-8, 300, prec == amg.AMG_FP32)
+                torch.cuda.synchronize()
+                dt = time.time() - t
+                tr = np.linalg.norm(b - As @ host(x)) / nb
+                _log(f"C5 prec {prec} kind {kind}: rc {rc} iters {it} relres {rel:.2e} true {tr:.2e} {dt:.2f} s")
+                assert rc == amg.AMG_OK and tr <= 2e-8
+
+
+def test_c3_fp32_vs_fp64_full_size():
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    t = time.time()
+    A, b, _ = W.config_problem(3)
+    _log(f"C3 assembled: n={A.n} nnz={A.nnz} in {time.time() - t:.0f} s")
+    As = A.to_scipy()
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    xs = {}
+    for prec in (amg.AMG_FP64, amg.AMG_FP32):
+        with hierarchy(A, precision=prec) as h:
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 300, prec == amg.AMG_FP32)
+            torch.cuda.synchronize()
+            xs[prec] = host(x)
+            tr = np.linalg.norm(b - As @ xs[prec]) / nb
+            _log(f"C3 prec {prec}: rc {rc} iters {it} relres {rel:.2e} true {tr:.2e}")
+            assert rc == amg.AMG_OK and tr <= 2e-8
+    e = np.linalg.norm(xs[amg.AMG_FP32] - xs[amg.AMG_FP64]) / np.linalg.norm(xs[amg.AMG_FP64])
+    _log(f"C3 FP32-hierarchy solution vs FP64: relative difference {e:.2e}")
+    assert e <= 1e-6

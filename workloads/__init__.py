@@ -66,7 +66,7 @@ class CSR:
         return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
 
 
-def stencil_csr(grid, offsets, values):
+def stencil_csr(grid, offsets, values, planes_per_chunk=None):
     """Assemble a CSR matrix from a stencil on an (nx, ny, nz) interior grid.
 
     ``offsets`` is a list of (dx, dy, dz); ``values[m]`` is either a scalar or
@@ -74,43 +74,54 @@ def stencil_csr(grid, offsets, values):
     places on its neighbour (i+dx, j+dy, k+dz).  Neighbours outside the grid
     are dropped (Dirichlet elimination).  Entries are stored even when their
     value is exactly zero (the stencil pattern, not the values, fixes nnz).
+    Rows are built a few z-planes at a time as dense (rows x stencil) blocks
+    compressed by the validity mask, which keeps memory bounded.
     """
     nx, ny, nz = grid
     n = nx * ny * nz
     order = sorted(range(len(offsets)), key=lambda m: (offsets[m][2], offsets[m][1], offsets[m][0]))
-    kk, jj, ii = np.meshgrid(np.arange(nz, dtype=np.int32), np.arange(ny, dtype=np.int32),
-                             np.arange(nx, dtype=np.int32), indexing="ij")
-    masks = []
-    counts = np.zeros((nz, ny, nx), dtype=np.int32)
-    for m in order:
-        dx, dy, dz = offsets[m]
-        mk = ((ii + dx >= 0) & (ii + dx < nx) & (jj + dy >= 0) & (jj + dy < ny)
-              & (kk + dz >= 0) & (kk + dz < nz))
-        masks.append(mk)
-        counts += mk
+    offs = np.array([offsets[m] for m in order], dtype=np.int64)
+    vals = [values[m] for m in order]
+    M = len(order)
+    vx = (np.arange(nx)[:, None] + offs[None, :, 0] >= 0) & (np.arange(nx)[:, None] + offs[None, :, 0] < nx)
+    vy = (np.arange(ny)[:, None] + offs[None, :, 1] >= 0) & (np.arange(ny)[:, None] + offs[None, :, 1] < ny)
+    vz = (np.arange(nz)[:, None] + offs[None, :, 2] >= 0) & (np.arange(nz)[:, None] + offs[None, :, 2] < nz)
+    plane_cnt = (vy[:, None, :] & vx[None, :, :])  # (ny, nx, M)
+    counts = np.empty(n, dtype=np.int64)
+    for k in range(nz):
+        counts[k * nx * ny:(k + 1) * nx * ny] = (plane_cnt & vz[k][None, None, :]).sum(axis=2).ravel()
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts.ravel(), out=row_ptr[1:])
+    np.cumsum(counts, out=row_ptr[1:])
     nnz = int(row_ptr[-1])
     if nnz >= 2**31:
         raise ValueError("nnz exceeds int32 range")
     col = np.empty(nnz, dtype=np.int32)
     val = np.empty(nnz, dtype=np.float64)
-    cursor = row_ptr[:-1].copy()
-    rows = np.arange(n, dtype=np.int64)
-    del kk, jj, ii
-    for m, mk in zip(order, masks):
-        dx, dy, dz = offsets[m]
-        flat = mk.ravel()
-        pos = cursor[flat]
-        r = rows[flat]
-        col[pos] = (r + dx + nx * dy + nx * ny * dz).astype(np.int32)
-        v = values[m]
-        if np.isscalar(v):
-            val[pos] = float(v)
+    delta = (offs[:, 0] + nx * offs[:, 1] + nx * ny * offs[:, 2]).astype(np.int32)
+    kc = planes_per_chunk or max(1, (1 << 20) // (nx * ny))
+    rows_max = min(nz, kc) * nx * ny
+    # chunk buffers reused across chunks (first-touch allocation dominates otherwise)
+    cols = np.empty((rows_max, M), dtype=np.int32)
+    block = np.empty((rows_max, M), dtype=np.float64)
+    mask = np.empty((rows_max, M), dtype=bool)
+    base = np.arange(rows_max, dtype=np.int32)
+    all_scalar = all(np.isscalar(v) for v in vals)
+    scalar_row = np.array([float(v) for v in vals]) if all_scalar else None
+    for k0 in range(0, nz, kc):
+        k1 = min(nz, k0 + kc)
+        r0, r1 = k0 * nx * ny, k1 * nx * ny
+        m_ = mask[:r1 - r0]
+        np.logical_and(plane_cnt[None, :, :, :], vz[k0:k1, None, None, :], out=m_.reshape(k1 - k0, ny, nx, M))
+        c_ = cols[:r1 - r0]
+        np.add(base[:r1 - r0, None], np.int32(r0) + delta[None, :], out=c_)
+        col[row_ptr[r0]:row_ptr[r1]] = c_[m_]
+        b_ = block[:r1 - r0]
+        if all_scalar:
+            b_[...] = scalar_row[None, :]
         else:
-            val[pos] = np.asarray(v, dtype=np.float64).ravel()[flat]
-        cursor[flat] += 1
-        del pos, r, flat
+            for m, v in enumerate(vals):
+                b_[:, m] = v if np.isscalar(v) else np.asarray(v, dtype=np.float64)[k0:k1].ravel()
+        val[row_ptr[r0]:row_ptr[r1]] = b_[m_]
     return CSR(n=n, row_ptr=row_ptr.astype(np.int32), col=col, val=val, grid=(nx, ny, nz))
 
 
