@@ -285,7 +285,17 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     roofline["copy_GBps"] = round(copy_gbs, 1)
-    del src, dst
+    del dst
+    src2 = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB read by a reduction
+    src2.sum()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        src2.sum()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    roofline["read_GBps"] = round(src2.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, src2
 
     # ---- variants: other kinds, FP32 hierarchy ----
     variants = {}

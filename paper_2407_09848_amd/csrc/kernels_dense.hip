@@ -182,8 +182,8 @@ __global__ __launch_bounds__(256) void k_gemv(int np, const double* __restrict__
 // part[p][row block][column block]; a second kernel sums them in a fixed order.
 // b and x are level vectors (nl rows per problem); padding rows read as 0.
 template <typename T>
-__global__ __launch_bounds__(64) void k_symv_blocks(int nb, int64_t nl, int64_t np, const double* __restrict__ Ainv,
-                                                    const T* __restrict__ b, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_symv_blocks(int nb, int64_t nl, int64_t np, const double* __restrict__ Ainv,
+                                                     const T* __restrict__ b, double* __restrict__ part) {
   __shared__ double tile[TM][TM + 1];
   __shared__ double bi[TM], bj[TM];
   const int p = blockIdx.y;
@@ -193,32 +193,48 @@ __global__ __launch_bounds__(64) void k_symv_blocks(int nb, int64_t nl, int64_t 
   while ((J + 1) * (J + 2) / 2 <= q) ++J;
   while (J * (J + 1) / 2 > q) --J;
   const int I = q - J * (J + 1) / 2;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const double* A = Ainv + (int64_t)p * np * np;
   const T* bp = b + (int64_t)p * nl;
-  const int64_t ri = (int64_t)I * TM + t, rj = (int64_t)J * TM + t;
-  bi[t] = ri < nl ? (double)bp[ri] : 0.0;
-  bj[t] = rj < nl ? (double)bp[rj] : 0.0;
-  for (int a = 0; a < TM; ++a) tile[a][t] = A[((int64_t)J * TM + a) * np + (int64_t)I * TM + t];
+  if (w == 0) {
+    const int64_t ri = (int64_t)I * TM + lane;
+    bi[lane] = ri < nl ? (double)bp[ri] : 0.0;
+  } else if (w == 1) {
+    const int64_t rj = (int64_t)J * TM + lane;
+    bj[lane] = rj < nl ? (double)bp[rj] : 0.0;
+  }
+  // each wave loads 16 rows of the tile, one 512 B row segment per load
+  for (int a = w; a < TM; a += 4) tile[a][lane] = A[((int64_t)J * TM + a) * np + (int64_t)I * TM + lane];
   __syncthreads();
-  double row = 0.0, colsum = 0.0;
-  for (int c = 0; c < TM; ++c) row += tile[t][c] * bi[c];  // (A_JI b_I)_t
   double* out = part + (int64_t)p * nb * nb * TM;
-  out[((int64_t)J * nb + I) * TM + t] = row;
-  if (J > I) {
-    for (int a = 0; a < TM; ++a) colsum += tile[a][t] * bj[a];  // (A_JI^T b_J)_t
-    out[((int64_t)I * nb + J) * TM + t] = colsum;
+  if (w == 0) {
+    double row = 0.0;  // (A_JI b_I)_lane
+    for (int c = 0; c < TM; ++c) row += tile[lane][c] * bi[c];
+    out[((int64_t)J * nb + I) * TM + lane] = row;
+  } else if (w == 1 && J > I) {
+    double col = 0.0;  // (A_JI^T b_J)_lane
+    for (int a = 0; a < TM; ++a) col += tile[a][lane] * bj[a];
+    out[((int64_t)I * nb + J) * TM + lane] = col;
   }
 }
 
+// x_I = sum_J part[I][J]: four waves each sum a quarter of the J range, combined in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(TM) void k_symv_sum(int nb, int64_t nl, const double* __restrict__ part, T* __restrict__ x) {
-  const int p = blockIdx.y, I = blockIdx.x, t = threadIdx.x;
-  const int64_t row = (int64_t)I * TM + t;
+__global__ __launch_bounds__(256) void k_symv_sum(int nb, int64_t nl, const double* __restrict__ part,
+                                                  T* __restrict__ x) {
+  __shared__ double sm[4][TM];
+  const int p = blockIdx.y, I = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* in = part + (int64_t)p * nb * nb * TM + (int64_t)I * nb * TM;
+  const int per = (nb + 3) / 4;
   double s = 0.0;
-  for (int J = 0; J < nb; ++J) s += in[(int64_t)J * TM + t];
-  if (row < nl) x[(int64_t)p * nl + row] = (T)s;
+  for (int J = w * per; J < min(nb, (w + 1) * per); ++J) s += in[(int64_t)J * TM + lane];
+  sm[w][lane] = s;
+  __syncthreads();
+  if (w == 0) {
+    const double tot = ((sm[0][lane] + sm[1][lane]) + sm[2][lane]) + sm[3][lane];
+    const int64_t row = (int64_t)I * TM + lane;
+    if (row < nl) x[(int64_t)p * nl + row] = (T)tot;
+  }
 }
 
 template <bool TA, bool TB>
@@ -294,8 +310,8 @@ template <typename T>
 int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,
                        double* part) {
   const int nb = (int)(np / TM);
-  hipLaunchKernelGGL(k_symv_blocks<T>, dim3(nb * (nb + 1) / 2, nbatch), dim3(TM), 0, s, nb, nl, np, ainv, b, part);
-  hipLaunchKernelGGL(k_symv_sum<T>, dim3(nb, nbatch), dim3(TM), 0, s, nb, nl, (const double*)part, x);
+  hipLaunchKernelGGL(k_symv_blocks<T>, dim3(nb * (nb + 1) / 2, nbatch), dim3(256), 0, s, nb, nl, np, ainv, b, part);
+  hipLaunchKernelGGL(k_symv_sum<T>, dim3(nb, nbatch), dim3(256), 0, s, nb, nl, (const double*)part, x);
   return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
 }
 template int launch_coarse_symv<double>(hipStream_t, int, int64_t, int64_t, const double*, const double*, double*,

@@ -571,7 +571,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   // CG and reduction workspace
   const int64_t n0 = h->lv[0].n;
   const int64_t maxblocks = ((n0 + kBlock - 1) / kBlock + 7) / 8 * 8 + 8;
-  AMGP_TRY(dalloc(&h->partial, 2 * maxblocks));
+  AMGP_TRY(dalloc(&h->partial, 2 * maxblocks + 2 * 64));  // + the middle-stage sums of long lists
   AMGP_TRY(dalloc(&h->scal, S_NSCAL));
   if (hipHostMalloc((void**)&h->hscal, sizeof(double) * (S_NSCAL + F_NFLAG)) != hipSuccess) return AMG_ENOMEM;
   AMGP_TRY(dalloc(&h->cg_r, n0));
