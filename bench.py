@@ -93,13 +93,14 @@ def measured_traffic(size):
     has changed since the counters were taken."""
     import hashlib
     import re
-    if size != 128:
+    path = os.path.join(ROOT, "profiles", f"fused_step_poisson{size}.md")
+    if not os.path.exists(path):
         return None
     try:
         src = open(os.path.join(ROOT, "paper_2407_09848_amd", "csrc", "kernels_sparse.hip")).read()
         a = src.index("\n", src.index("// BEGIN fused-step")) + 1
         digest = hashlib.sha256(src[a:src.index("// END fused-step")].encode()).hexdigest()[:16]
-        prof = open(os.path.join(ROOT, "profiles", "fused_step_poisson128.md")).read()
+        prof = open(path).read()
         if re.search(r"sha256 prefix: (\w+)", prof).group(1) != digest:
             return None
         return int(re.search(r"traffic_bytes_per_launch: (\d+)", prof).group(1))
@@ -268,7 +269,7 @@ def main():
     achieved = fused_bytes / (t_fused_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM, 4), "traffic": measured_traffic(args.size),
-                "kernel": "k_fused<double,0,true> (fine level, 128^3)",
+                "kernel": f"k_fused<double,0,true> (fine level, {args.size}^3)",
                 "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2)}
 
     # ---- plain device copy of 1 GiB: measured copy bandwidth, and the reference

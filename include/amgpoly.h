@@ -17,6 +17,9 @@
  * Galerkin products A_{l+1} = P^T A_l P with P piecewise constant on fixed
  * 2x2x2 boxes of the structured grid (Section 2, first display); the
  * coarsest level is solved directly (dense Cholesky, factor formed at setup).
+ * Setup options give the ingredients of the paper's own runs (Section 4):
+ * boxes of another edge, the smoothed prolongator and a coarsest solve by a
+ * fixed number of l1-Jacobi sweeps.
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device (HBM) pointers; pointers named h_* are
@@ -50,7 +53,7 @@ extern "C" {
 #define AMG_EHIP          -4  /* a HIP runtime call failed */
 #define AMG_EBREAKDOWN    -5  /* CG breakdown: (p, A p) <= 0 */
 #define AMG_ENAN          -6  /* non-finite value in the input or the iteration */
-#define AMG_ECAPACITY     -7  /* a coarse row exceeds the Galerkin kernel's column capacity */
+#define AMG_ECAPACITY     -7  /* a product row exceeds the Galerkin kernels' column capacity */
 
 /* ---- smoother kinds ---- */
 #define AMG_L1JAC     0
@@ -74,6 +77,13 @@ typedef struct amg_opts {
   int32_t nbatch;       /* >= 1 problems stacked along z (block-diagonal A); 0 means 1 */
   int32_t max_coarse;   /* coarsen while rows per problem > max_coarse; 0 means 4096 */
   int32_t precision;    /* AMG_FP64 or AMG_FP32 */
+  /* The preconditioner ingredients of Section 4 (all zero: 2x2x2 boxes, plain
+   * aggregation, dense Cholesky coarsest solve). */
+  int32_t agg_edge;      /* box aggregate edge in 2..4; 0 means 2 */
+  int32_t smoothed;      /* 1: smoothed prolongator P = (I - omega D^{-1} A) P_hat, D = diag(A),
+                            omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem (Section 4) */
+  int32_t coarse_sweeps; /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps from
+                            zero (at most 1000) instead of the dense Cholesky factorisation */
 } amg_opts;
 
 /* ---------------------------------------------------------------------------
@@ -87,8 +97,14 @@ typedef struct amg_opts {
  * level's l1 diagonal, the box aggregates, the Galerkin operators, the
  * sliced-ELL copies used by the kernels and the coarsest factor, and
  * allocates all workspace.  Synchronises `stream`.
+ * With agg_edge != 2 or smoothed != 0 the transfers use explicit P and P^T
+ * (sliced ELL), built with general sparse products; entries of the smoothed P
+ * and of the Galerkin operators whose magnitude is at most 2^-46 times the
+ * largest of their row are dropped (exact cancellations up to rounding).
  * Errors: AMG_EINVAL (null, n mismatch, nnz < n, a row_ptr that is not monotone from
- * 0 to nnz, a column index out of range or not increasing in its row), AMG_ENOTSPD, AMG_ECAPACITY,
+ * 0 to nnz, a column index out of range or not increasing in its row, an option out
+ * of range), AMG_ENOTSPD, AMG_ECAPACITY (a product row with more than 3072 distinct
+ * columns),
  * AMG_ENOMEM, AMG_EHIP.  On error *out is NULL.
  * ------------------------------------------------------------------------- */
 int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
@@ -170,6 +186,20 @@ int vcycle_apply(amg_handle* h, int kind, int degree, const double* d_r, double*
 int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_x, int x_is_zero,
               double rtol, int maxit, int flexible, int* h_iters, double* h_relres,
               double* h_hist, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Preconditioned CG with the level-0 smoother alone as the preconditioner:
+ * z = p_k(M^{-1}A) M^{-1} r, the degree-k `kind` polynomial of l1-Jacobi run
+ * from z = 0 (the polynomial preconditioning of the remark after
+ * Fig. boundcomparison, Fig. better-than-optimal).  No coarse correction is
+ * applied, so the hierarchy below level 0 is unused (a single-level handle,
+ * n <= max_coarse, is the natural setup).  The smoother always runs in
+ * float64, also in AMG_FP32 handles.  Arguments, outputs, synchronisation and
+ * return codes are those of pcg_solve.
+ * ------------------------------------------------------------------------- */
+int pcg_solve_smoother(amg_handle* h, int kind, int degree, const double* d_b, double* d_x,
+                       int x_is_zero, double rtol, int maxit, int flexible, int* h_iters,
+                       double* h_relres, double* h_hist, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Differentiable V-cycle and the learned optimal-4th-kind weights.

@@ -1,13 +1,19 @@
 """Aggregation AMG hierarchy, V-cycle and PCG (oracle, test infrastructure only).
 
 * Galerkin coarse operators A_{l+1} = P_l^T A_l P_l (Section 2, first display).
-* Piecewise-constant P from fixed 2x2x2 box aggregates of the structured
-  grid (entries 1.0; a dimension of extent 1 is not coarsened, an odd extent
-  leaves a last aggregate one cell wide).  Problems stacked along z
-  (``nbatch`` > 1) are aggregated separately.
+* Piecewise-constant P from fixed box aggregates of the structured grid,
+  2x2x2 by default, e x e x e for an aggregate edge e (entries 1.0; a
+  dimension of extent 1 is not coarsened, a ragged extent leaves a last
+  aggregate narrower than e).  Problems stacked along z (``nbatch`` > 1) are
+  aggregated separately.
+* Optionally the smoothed prolongator of Section 4, P = (I - omega D^{-1} A) P_hat
+  with D the diagonal of A and omega = 4 / (3 lambda), lambda an estimate of
+  the largest eigenvalue of D^{-1} A; the estimate used is the Gershgorin bound
+  ||D^{-1} A||_inf, taken per stacked problem.
 * Coarsening continues while a level has more than ``max_coarse`` rows per
   problem; the coarsest level is solved by dense Cholesky (scipy cho_factor /
-  cho_solve), one factor per stacked problem.
+  cho_solve), one factor per stacked problem, or, as in the paper's runs
+  (Section 4), by a fixed number of l1-Jacobi sweeps from zero.
 * V-cycle of eq. (amg): pre-smoothing with p_k(M^{-1}A) from zero, residual
   restriction, recursion, prolongation, post-smoothing with the same
   polynomial (M is diagonal and p_k(M^{-1}A) is A-self-adjoint, so the
@@ -26,7 +32,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import polynomials as P
-from .smoothers import OPTCHEB1, OPTCHEB4, l1_diagonal, smooth
+from .smoothers import OPTCHEB1, OPTCHEB4, l1_diagonal, smooth, smooth_l1jacobi
 
 
 @dataclass
@@ -42,26 +48,28 @@ class Level:
 class Hierarchy:
     levels: list = field(default_factory=list)
     chol: list = field(default_factory=list)  # cho_factor per stacked problem on the coarsest level
+    coarse_sweeps: int = 0  # > 0: the coarsest solve is this many l1-Jacobi sweeps from zero
 
     @property
     def L(self):
         return len(self.levels) - 1
 
 
-def box_aggregates(grid, nbatch=1):
+def box_aggregates(grid, nbatch=1, edge=2):
     """Aggregate index of every fine row and the coarse per-problem grid.
 
-    Fine row (i, j, k) of problem p belongs to coarse cell (i//2, j//2, k//2)
+    Fine row (i, j, k) of problem p belongs to coarse cell (i//e, j//e, k//e)
     of problem p (a dimension of extent 1 is kept); coarse rows are ordered
     problem-major, then lexicographically.
     """
     nx, ny, nz = grid
-    cx = nx if nx == 1 else (nx + 1) // 2
-    cy = ny if ny == 1 else (ny + 1) // 2
-    cz = nz if nz == 1 else (nz + 1) // 2
-    i = np.arange(nx) if nx == 1 else np.arange(nx) // 2
-    j = np.arange(ny) if ny == 1 else np.arange(ny) // 2
-    k = np.arange(nz) if nz == 1 else np.arange(nz) // 2
+    e = edge
+    cx = nx if nx == 1 else (nx + e - 1) // e
+    cy = ny if ny == 1 else (ny + e - 1) // e
+    cz = nz if nz == 1 else (nz + e - 1) // e
+    i = np.arange(nx) if nx == 1 else np.arange(nx) // e
+    j = np.arange(ny) if ny == 1 else np.arange(ny) // e
+    k = np.arange(nz) if nz == 1 else np.arange(nz) // e
     agg1 = (i[None, None, :] + cx * j[None, :, None] + cx * cy * k[:, None, None]).ravel()
     nc1 = cx * cy * cz
     agg = np.concatenate([agg1 + p * nc1 for p in range(nbatch)])
@@ -73,26 +81,77 @@ def prolongator(agg, nc):
     return sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, nc))
 
 
-def build_hierarchy(A, grid, nbatch=1, max_coarse=4096):
-    """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse."""
+def jacobi_weight(A, nbatch=1):
+    """omega = 4 / (3 lambda) of the smoothed prolongator, one value per stacked problem, with
+    lambda = ||D^{-1} A||_inf (max over the problem's rows of sum_j |a_ij| / a_ii), an upper
+    bound of the largest eigenvalue of D^{-1} A (Gershgorin)."""
+    A = sp.csr_matrix(A)
+    d = A.diagonal()
+    rows = np.asarray(abs(A).sum(axis=1)).ravel() / d
+    per = A.shape[0] // nbatch
+    return np.array([4.0 / (3.0 * rows[p * per:(p + 1) * per].max()) for p in range(nbatch)])
+
+
+DROP_TAU = 2.0**-46
+
+
+def drop_small(M, tau=DROP_TAU):
+    """Remove the entries of a computed product whose magnitude is at most tau times the largest
+    of their row: with the smoothed prolongator, entries that cancel exactly in exact arithmetic
+    come out of the products as rounding residue (~1e-17) in an order-dependent way."""
+    M = sp.csr_matrix(M)
+    rowmax = np.zeros(M.shape[0])
+    np.maximum.at(rowmax, np.repeat(np.arange(M.shape[0]), np.diff(M.indptr)), np.abs(M.data))
+    keep = np.abs(M.data) > tau * np.repeat(rowmax, np.diff(M.indptr))
+    rows = np.repeat(np.arange(M.shape[0]), np.diff(M.indptr))[keep]
+    out = sp.csr_matrix((M.data[keep], (rows, M.indices[keep])), shape=M.shape)
+    out.sort_indices()
+    return out
+
+
+def smoothed_prolongator(A, Phat, nbatch=1):
+    """P = (I - omega D^{-1} A) P_hat (Section 4), omega from jacobi_weight per stacked problem."""
+    A = sp.csr_matrix(A)
+    omega = np.repeat(jacobi_weight(A, nbatch), A.shape[0] // nbatch)
+    S = sp.diags(omega / A.diagonal())
+    return (Phat - S @ (A @ Phat)).tocsr()
+
+
+def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=False, coarse_sweeps=0):
+    """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse.
+
+    ``agg_edge``: edge of the box aggregates; ``smoothed``: use the smoothed
+    prolongator; ``coarse_sweeps`` > 0: solve the coarsest level by that many
+    l1-Jacobi sweeps from zero instead of the dense Cholesky factorisation.
+    Outside the default (2x2x2 boxes, plain P) the smoothed P and the Galerkin
+    operators pass through drop_small.
+    """
     A = sp.csr_matrix(A)
     A.sort_indices()
-    H = Hierarchy()
+    H = Hierarchy(coarse_sweeps=int(coarse_sweeps))
     g = tuple(grid)
     if nbatch > 1:
         g = (g[0], g[1], g[2] // nbatch)
     H.levels.append(Level(A=A, Minv=l1_diagonal(A), grid=g, nbatch=nbatch))
     while A.shape[0] // nbatch > max_coarse:
-        agg, gc = box_aggregates(g, nbatch)
+        agg, gc = box_aggregates(g, nbatch, agg_edge)
         nc = int(np.prod(gc)) * nbatch
         if nc >= A.shape[0]:
             raise ValueError("aggregation does not reduce the level")
         Pm = prolongator(agg, nc)
+        general = smoothed or agg_edge != 2
+        if smoothed:
+            Pm = drop_small(smoothed_prolongator(A, Pm, nbatch))
+        Pm.sort_indices()
         Ac = (Pm.T @ A @ Pm).tocsr()
+        if general:
+            Ac = drop_small(Ac)
         Ac.sort_indices()
         H.levels[-1].P = Pm
         A, g = Ac, gc
         H.levels.append(Level(A=A, Minv=l1_diagonal(A), grid=g, nbatch=nbatch))
+    if H.coarse_sweeps > 0:
+        return H
     nL = A.shape[0] // nbatch
     dense = A.toarray()
     for p in range(nbatch):
@@ -102,7 +161,10 @@ def build_hierarchy(A, grid, nbatch=1, max_coarse=4096):
 
 
 def coarse_solve(H, b):
-    nb = H.levels[-1].nbatch
+    lv = H.levels[-1]
+    if H.coarse_sweeps > 0:
+        return smooth_l1jacobi(lv.A, lv.Minv, b, None, H.coarse_sweeps)
+    nb = lv.nbatch
     nL = b.size // nb
     out = np.empty_like(b)
     for p in range(nb):
@@ -186,9 +248,9 @@ def pcg(A, b, precond, rtol=1e-8, maxit=1000, flexible=False):
 
 
 def amg_pcg(A, b, grid, kind, k, nbatch=1, max_coarse=4096, rtol=1e-8, maxit=1000, H=None,
-            flexible=False, beta=None):
+            flexible=False, beta=None, **hierarchy_opts):
     """Set up the hierarchy (unless given) and solve A x = b with the V-cycle-preconditioned CG."""
     if H is None:
-        H = build_hierarchy(A, grid, nbatch, max_coarse)
+        H = build_hierarchy(A, grid, nbatch, max_coarse, **hierarchy_opts)
     res = pcg(H.levels[0].A, b, lambda r: vcycle(H, r, kind, k, beta), rtol, maxit, flexible)
     return res, H

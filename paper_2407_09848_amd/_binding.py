@@ -16,7 +16,7 @@ __all__ = [
     "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info",
     "amg_level_export", "amg_default_beta", "amg_default_astar", "amg_set_beta", "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
-    "vcycle_apply", "pcg_solve", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
+    "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
     "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_adam",
     "amg_beta_valid", "VCycleFunction",
     "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
@@ -27,7 +27,8 @@ __all__ = [
 
 class AmgOpts(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("nbatch", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("nbatch", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("agg_edge", ctypes.c_int32), ("smoothed", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32)]
 
 
 class AmgError(RuntimeError):
@@ -60,6 +61,8 @@ _SIGS = {
     "vcycle_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "pcg_solve": (_I, [_P, _I, _I, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
                        ctypes.POINTER(_D), _P]),
+    "pcg_solve_smoother": (_I, [_P, _I, _I, _P, _P, _I, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
+                                ctypes.POINTER(_D), _P]),
     "amg_strerror": (ctypes.c_char_p, [_I]),
     "amg_ckpt_bytes": (_I, [_P, ctypes.POINTER(_I64)]),
     "vcycle_fwd_ckpt": (_I, [_P, _I, _P, _P, _P, _P, _P]),
@@ -119,12 +122,13 @@ def amg_strerror(code: int) -> str:
     return lib().amg_strerror(code).decode()
 
 
-def amg_setup(row_ptr, col, val, nx, ny, nz, nbatch=1, max_coarse=4096, precision=AMG_FP64):
+def amg_setup(row_ptr, col, val, nx, ny, nz, nbatch=1, max_coarse=4096, precision=AMG_FP64, agg_edge=2,
+              smoothed=False, coarse_sweeps=0):
     """Build the hierarchy for the device CSR matrix (int32 row_ptr/col, float64 val); returns the handle."""
     import torch
     n = row_ptr.numel() - 1
     nnz = col.numel()
-    o = AmgOpts(nx, ny, nz, nbatch, max_coarse, precision)
+    o = AmgOpts(nx, ny, nz, nbatch, max_coarse, precision, agg_edge, int(bool(smoothed)), coarse_sweeps)
     h = ctypes.c_void_p()
     rc = lib().amg_setup(n, nnz, _ptr(row_ptr, torch.int32, name="row_ptr"), _ptr(col, torch.int32, name="col"),
                          _ptr(val, torch.float64, nnz, "val"), ctypes.byref(o), _stream(), ctypes.byref(h))
@@ -230,17 +234,28 @@ def vcycle_apply(h, kind, degree, r, z):
                                      _stream()), "vcycle_apply")
 
 
-def pcg_solve(h, kind, degree, b, x, x_is_zero=True, rtol=1e-8, maxit=1000, flexible=False, history=False):
-    """Returns (rc, iters, relres, hist list or None); rc is AMG_OK or AMG_NOT_CONVERGED (errors raise)."""
+def _pcg(name, h, kind, degree, b, x, x_is_zero, rtol, maxit, flexible, history):
     import torch
     n, _ = amg_level_info(h, 0)
     it, rel = _I(), _D()
     hist = (_D * (maxit + 1))() if history else None
-    rc = lib().pcg_solve(h, kind, degree, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"),
-                         int(bool(x_is_zero)), float(rtol), int(maxit), int(bool(flexible)), ctypes.byref(it),
-                         ctypes.byref(rel), hist, _stream())
-    _check(rc, "pcg_solve", allow=(AMG_OK, AMG_NOT_CONVERGED))
+    rc = getattr(lib(), name)(h, kind, degree, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64, n, "x"),
+                              int(bool(x_is_zero)), float(rtol), int(maxit), int(bool(flexible)), ctypes.byref(it),
+                              ctypes.byref(rel), hist, _stream())
+    _check(rc, name, allow=(AMG_OK, AMG_NOT_CONVERGED))
     return rc, it.value, rel.value, ([hist[i] for i in range(it.value + 1)] if history else None)
+
+
+def pcg_solve(h, kind, degree, b, x, x_is_zero=True, rtol=1e-8, maxit=1000, flexible=False, history=False):
+    """V-cycle-preconditioned CG.  Returns (rc, iters, relres, hist list or None); rc is AMG_OK or
+    AMG_NOT_CONVERGED (errors raise)."""
+    return _pcg("pcg_solve", h, kind, degree, b, x, x_is_zero, rtol, maxit, flexible, history)
+
+
+def pcg_solve_smoother(h, kind, degree, b, x, x_is_zero=True, rtol=1e-8, maxit=1000, flexible=False,
+                       history=False):
+    """CG preconditioned by the level-0 polynomial smoother alone; same returns as pcg_solve."""
+    return _pcg("pcg_solve_smoother", h, kind, degree, b, x, x_is_zero, rtol, maxit, flexible, history)
 
 
 # ---------------------------------------------------------------------------

@@ -75,8 +75,24 @@ struct Level {
   // transfer to level + 1
   int64_t nc = 0;                 // rows of level + 1
   int32_t* agg = nullptr;         // [n] aggregate of each row
-  int32_t* children = nullptr;    // [nc * 8] rows of each aggregate, ascending, -1 padded
+  int32_t* children = nullptr;    // [nc * 8] rows of each aggregate, ascending, -1 padded (2x2x2 boxes)
+  // explicit prolongator (smoothed, or boxes of another edge): P (n x nc) and P^T (nc x n)
+  bool general = false;
+  Ell<double> P64, PT64;
+  Ell<float> P32, PT32;
 };
+
+// Device CSR matrix (m x ncols) used by the setup's general sparse products.
+struct Csr {
+  int64_t m = 0, ncols = 0, nnz = 0;
+  int32_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+};
+
+// Entries of a computed product whose magnitude is at most kDropTau times the
+// largest of their row are dropped (exact cancellations up to rounding).
+constexpr double kDropTau = 1.4210854715202004e-14;  // 2^-46
 
 // A captured V-cycle (one launch sequence for a given kind, degree and r/z buffers).
 struct GraphEntry {
@@ -113,6 +129,9 @@ struct Handle {
   int nbatch = 1;
   int precision = AMG_FP64;
   int max_coarse = 4096;
+  int agg_edge = 2;       // box aggregate edge
+  bool smoothed = false;  // smoothed prolongator
+  int coarse_sweeps = 0;  // > 0: l1-Jacobi sweeps instead of the dense coarsest solve
   std::vector<Level> lv;
   // coarsest level: dense inverse per problem, padded to ncp
   int64_t ncl = 0;   // rows per problem on the coarsest level
@@ -188,6 +207,8 @@ int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* c
                     const T* x, T* tmp, T* bc);
 template <typename T>
 int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x);
+template <typename T>
+int launch_spmv_add(hipStream_t s, const Ell<T>& A, const T* x, T* y);  // y += A x
 // vectors
 template <typename T>
 int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av = Wt());  // y += a x
@@ -247,10 +268,12 @@ int launch_offdiag_ratio(hipStream_t s, int64_t n, const int32_t* ptr, const int
 int validate_csr(hipStream_t s, int64_t n, int64_t nnz, const int32_t* ptr, const int32_t* col, int* flag);
 int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
                    double* minv, int* flag);
+// ncols: number of columns (default n); padding entries use column i when i < ncols, else 0
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
-                Ell<double>* out);
+                Ell<double>* out, int64_t ncols = -1);
 int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out);
-int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int32_t* agg, int32_t* children,
+// box aggregates of edge e; children (2x2x2 boxes only) may be null
+int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int e, int32_t* agg, int32_t* children,
                       int* cnx, int* cny, int* cnz);
 int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
              const int32_t* agg, int64_t nc, const int32_t* children, int32_t** cptr, int32_t** ccol,
@@ -258,6 +281,16 @@ int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, c
 int launch_to_dense(hipStream_t s, int nbatch, int64_t nl, int64_t np, const int32_t* ptr, const int32_t* col,
                     const double* val, double* dense, int* flag);
 void free_ell(Ell<double>& e);
+// ---- general sparse products (kernels_galerkin.hip) ----
+void free_csr(Csr& a);
+int spgemm(hipStream_t s, const Csr& X, const Csr& Y, Csr* C, int* flag);  // C = X Y
+int drop_small(hipStream_t s, Csr* a, double tau);
+int transpose(hipStream_t s, const Csr& a, Csr* t);
+int tentative_prolongator(hipStream_t s, int64_t n, int64_t nc, const int32_t* agg, Csr* P);
+// P = (I - omega D^{-1} A) P_hat, omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem
+int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const int32_t* agg, int64_t nc, Csr* P,
+                         int* flag);
+int galerkin_general(hipStream_t s, const Csr& A, const Csr& P, const Csr& PT, Csr* Ac, int* flag);
 void free_ell(Ell<float>& e);
 
 // ---- dense kernels (kernels_dense.hip) ----

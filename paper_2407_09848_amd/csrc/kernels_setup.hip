@@ -67,7 +67,7 @@ __global__ void k_slice_width(int64_t n, int64_t nslices, const int32_t* __restr
   w[s] = m;
 }
 
-__global__ void k_ell_fill(int64_t n, int64_t nslices, const int32_t* __restrict__ ptr,
+__global__ void k_ell_fill(int64_t n, int64_t ncols, int64_t nslices, const int32_t* __restrict__ ptr,
                            const int32_t* __restrict__ col, const double* __restrict__ val,
                            const int32_t* __restrict__ sptr, int32_t* __restrict__ ecol, double* __restrict__ eval) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,7 +81,7 @@ __global__ void k_ell_fill(int64_t n, int64_t nslices, const int32_t* __restrict
     p0 = ptr[i];
     len = ptr[i + 1] - p0;
   }
-  const int32_t padcol = i < n ? (int32_t)i : 0;
+  const int32_t padcol = (i < n && i < ncols) ? (int32_t)i : 0;
   for (int j = 0; j < width; ++j) {
     const int64_t q = base + (int64_t)j * kSlice + lane;
     if (j < len) {
@@ -99,16 +99,16 @@ __global__ void k_round_f32(int64_t m, const double* __restrict__ a, float* __re
   if (i < m) b[i] = (float)a[i];
 }
 
-// Box aggregates: row (i, j, k) of problem p -> coarse (i/2, j/2, k/2) of problem p;
-// an axis of extent 1 is not coarsened.  children[I*8 + c] lists the rows of
-// aggregate I in ascending order (z, then y, then x), -1 padded.
-__global__ void k_agg(int64_t n, int nx, int ny, int nz, int cx, int cy, int cz, int32_t* __restrict__ agg) {
+// Box aggregates of edge e: row (i, j, k) of problem p -> coarse (i/e, j/e, k/e) of
+// problem p; an axis of extent 1 is not coarsened.  For e = 2, children[I*8 + c]
+// lists the rows of aggregate I in ascending order (z, then y, then x), -1 padded.
+__global__ void k_agg(int64_t n, int nx, int ny, int nz, int e, int cx, int cy, int cz, int32_t* __restrict__ agg) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int64_t per = (int64_t)nx * ny * nz;
   const int64_t p = r / per, q = r % per;
   const int i = (int)(q % nx), j = (int)((q / nx) % ny), k = (int)(q / ((int64_t)nx * ny));
-  const int ci = nx == 1 ? i : i / 2, cj = ny == 1 ? j : j / 2, ck = nz == 1 ? k : k / 2;
+  const int ci = nx == 1 ? i : i / e, cj = ny == 1 ? j : j / e, ck = nz == 1 ? k : k / e;
   agg[r] = (int32_t)(p * (int64_t)cx * cy * cz + ci + (int64_t)cx * cj + (int64_t)cx * cy * ck);
 }
 
@@ -234,7 +234,8 @@ int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* 
 }
 
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
-                Ell<double>* out) {
+                Ell<double>* out, int64_t ncols) {
+  if (ncols < 0) ncols = n;
   Ell<double> e;
   e.n = n;
   e.nslices = (n + kSlice - 1) / kSlice;
@@ -258,8 +259,8 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
   if (hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(acc, 1)) != hipSuccess) return AMG_ENOMEM;
   if (hipMalloc(&e.val, sizeof(double) * std::max<int64_t>(acc, 1)) != hipSuccess) return AMG_ENOMEM;
   AMGP_HIP(hipMemcpyAsync(e.sptr, sp.data(), sizeof(int32_t) * (e.nslices + 1), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_ell_fill, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, n, e.nslices, ptr, col,
-                     val, e.sptr, e.col, e.val);
+  hipLaunchKernelGGL(k_ell_fill, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, n, ncols, e.nslices, ptr,
+                     col, val, e.sptr, e.col, e.val);
   AMGP_HIP(hipGetLastError());
   AMGP_HIP(hipStreamSynchronize(s));
   *out = e;
@@ -296,12 +297,15 @@ void free_ell(Ell<float>& e) {
   e = Ell<float>();
 }
 
-int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int32_t* agg, int32_t* children,
+int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int e, int32_t* agg, int32_t* children,
                       int* cnx, int* cny, int* cnz) {
-  const int cx = nx == 1 ? 1 : (nx + 1) / 2, cy = ny == 1 ? 1 : (ny + 1) / 2, cz = nz == 1 ? 1 : (nz + 1) / 2;
+  if (e < 2 || (children && e != 2)) return AMG_EINVAL;
+  const int cx = nx == 1 ? 1 : (nx + e - 1) / e, cy = ny == 1 ? 1 : (ny + e - 1) / e,
+            cz = nz == 1 ? 1 : (nz + e - 1) / e;
   const int64_t n = (int64_t)nx * ny * nz * nbatch, nc = (int64_t)cx * cy * cz * nbatch;
-  hipLaunchKernelGGL(k_agg, dim3(grid_for(n)), dim3(kBlock), 0, s, n, nx, ny, nz, cx, cy, cz, agg);
-  hipLaunchKernelGGL(k_children, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, nx, ny, nz, cx, cy, cz, children);
+  hipLaunchKernelGGL(k_agg, dim3(grid_for(n)), dim3(kBlock), 0, s, n, nx, ny, nz, e, cx, cy, cz, agg);
+  if (children)
+    hipLaunchKernelGGL(k_children, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, nx, ny, nz, cx, cy, cz, children);
   *cnx = cx;
   *cny = cy;
   *cnz = cz;

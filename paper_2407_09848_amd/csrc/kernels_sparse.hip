@@ -15,6 +15,9 @@ namespace amgp {
 
 namespace {
 
+// BEGIN fused-step (the launch helpers and the fused step; bench.py hashes this region to tie
+// stored counters to the code)
+
 constexpr int kXcd = 8;
 
 inline unsigned xcd_grid(int64_t n) {
@@ -46,7 +49,22 @@ __device__ __forceinline__ T wsel(const Wt& w, T scalar, int64_t i) {
   return w.v ? (T)w.v[(int)i / w.rpp * w.stride] : scalar;
 }
 
-template <typename T>
+// Levels larger than kRemapMaxBlocks blocks stream from HBM: there the matrix
+// and the row-local vectors are read and written with nontemporal hints (NT),
+// which keeps them from displacing the gathered vector in the caches
+// (measured at 256^3: 380 vs 424 us per fused step; on 128^3, whose working
+// set is close to the MALL, the hints cost 15-20%, so smaller levels keep the
+// default policy).  Gathered vectors always use ordinary loads and stores.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
+
+template <bool NT, typename T>
 __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restrict__ x) {
   // every lane of the wavefront is in the same slice: read its bounds once, as scalars
   const int s = __builtin_amdgcn_readfirstlane((int)(row >> 6));
@@ -56,7 +74,7 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
   T acc = T(0);
 #pragma unroll 4
   for (int p = beg + lane; p < end; p += kSlice) {
-    acc += A.val[p] * x[A.col[p]];
+    acc += ld<NT>(A.val + p) * x[ld<NT>(A.col + p)];
   }
   return acc;
 }
@@ -79,23 +97,22 @@ __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // SpMV and residual
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, EllView<T> A, const T* __restrict__ x,
                                                  T* __restrict__ y) {
   const int64_t i = row_index();
   if (i >= n) return;
-  y[i] = ell_dot(A, i, x);
+  st<NT>(y + i, ell_dot<NT>(A, i, x));
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r) {
   const int64_t i = row_index();
   if (i >= n) return;
-  r[i] = b[i] - ell_dot(A, i, x);
+  r[i] = ld<NT>(b + i) - ell_dot<NT>(A, i, x);
 }
 
-// BEGIN fused-step (bench.py hashes this region to tie stored counters to the code)
 // ---------------------------------------------------------------------------
 // Smoother recurrence steps.
 //
@@ -112,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 // carries an x update deferred by a first step that gathered x itself.
 // STORE = false on the last step of an application: only x is needed.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool STORE>
+template <typename T, int MODE, bool STORE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                   const T* __restrict__ gold, T* __restrict__ gnew,
                                                   const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
@@ -121,14 +138,15 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
   if (i >= n) return;
   w = wsel(wv, w, i);
   wprev = wsel(wpv, wprev, i);
-  const T ag = ell_dot(A, i, gold);
-  const T mi = minv[i];
+  const T ag = ell_dot<NT>(A, i, gold);
+  const T mi = ld<NT>(minv + i);
   const T go = gold[i];
-  const T r = (MODE == 0) ? rin[i] - ag : rin[i] - mi * ag;
+  const T ri = ld<NT>(rin + i);
+  const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
-  x[i] = x[i] + wprev * go + w * g;
+  st<NT>(x + i, ld<NT>(x + i) + wprev * go + w * g);
   if (STORE) {
-    rout[i] = r;
+    st<NT>(rout + i, r);
     gnew[i] = g;
   }
 }
@@ -137,24 +155,25 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
 
 // First step from x = 0 (r^(0) = b, no SpMV).
 // MODE 0: g = c M^{-1} b, x = w g.   MODE 1: r = M^{-1} b, g = r / c (c = theta), x = g.
-template <typename T, int MODE, bool STORE>
+template <typename T, int MODE, bool STORE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __restrict__ minv,
                                                        const T* __restrict__ b, T* __restrict__ g,
                                                        T* __restrict__ r, T* __restrict__ x, T c, T w, Wt wv) {
   const int64_t i = row_index();
   if (i >= n) return;
   w = wsel(wv, w, i);
-  const T mi = minv[i];
+  const T mi = ld<NT>(minv + i);
+  const T bi = ld<NT>(b + i);
   if (MODE == 0) {
-    const T gi = c * (mi * b[i]);
-    x[i] = w * gi;
+    const T gi = c * (mi * bi);
+    st<NT>(x + i, w * gi);
     if (STORE) g[i] = gi;
   } else {
-    const T ri = mi * b[i];
+    const T ri = mi * bi;
     const T gi = ri / c;
-    x[i] = gi;
+    st<NT>(x + i, gi);
     if (STORE) {
-      r[i] = ri;
+      st<NT>(r + i, ri);
       g[i] = gi;
     }
   }
@@ -166,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __res
 // vectors disappears.
 // MODE 0: g1 = c1 M^{-1} b, r1 = b - A g1, g2 = alpha g1 + c M^{-1} r1, x = w1 g1 + w2 g2.
 // MODE 1: r0 = M^{-1} b, d0 = r0 / theta, r1 = r0 - M^{-1} A d0, d1 = alpha d0 + c r1, x = d0 + d1.
-template <typename T, int MODE, bool STORE>
+template <typename T, int MODE, bool STORE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                         const T* __restrict__ b, T* __restrict__ gnew,
                                                         T* __restrict__ r, T* __restrict__ x, T c1, T alpha, T c,
@@ -181,9 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   T ag = T(0);
 #pragma unroll 4
   for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
-    const int j = A.col[p];
+    const int j = ld<NT>(A.col + p);
     const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-    ag += A.val[p] * g1j;
+    ag += ld<NT>(A.val + p) * g1j;
   }
   const T mi = minv[i];
   const T bi = b[i];
@@ -192,16 +211,16 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
     g1 = c1 * (mi * bi);
     r1 = bi - ag;
     g2 = alpha * g1 + c * (mi * r1);
-    x[i] = w1 * g1 + w2 * g2;
+    st<NT>(x + i, w1 * g1 + w2 * g2);
   } else {
     const T r0 = mi * bi;
     g1 = r0 / c1;
     r1 = r0 - mi * ag;
     g2 = alpha * g1 + c * r1;
-    x[i] = g1 + g2;
+    st<NT>(x + i, g1 + g2);
   }
   if (STORE) {
-    r[i] = r1;
+    st<NT>(r + i, r1);
     gnew[i] = g2;
   }
 }
@@ -209,20 +228,20 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
 // First step from a nonzero x: r^(0) from b - A x.  x is gathered here, so its
 // update is deferred to the next step (or a separate axpy when k = 1).
 // MODE 0: r = b - A x, g = c M^{-1} r.   MODE 1: r = M^{-1}(b - A x), g = r / c (c = theta).
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                       const T* __restrict__ b, const T* __restrict__ x,
                                                       T* __restrict__ r, T* __restrict__ g, T c) {
   const int64_t i = row_index();
   if (i >= n) return;
-  const T res = b[i] - ell_dot(A, i, x);
-  const T mi = minv[i];
+  const T res = ld<NT>(b + i) - ell_dot<NT>(A, i, x);
+  const T mi = ld<NT>(minv + i);
   if (MODE == 0) {
-    r[i] = res;
+    st<NT>(r + i, res);
     g[i] = c * (mi * res);
   } else {
     const T ri = mi * res;
-    r[i] = ri;
+    st<NT>(r + i, ri);
     g[i] = ri / c;
   }
 }
@@ -234,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, EllView<T> A, cons
                                                    T* __restrict__ xnew) {
   const int64_t i = row_index();
   if (i >= n) return;
-  xnew[i] = xold[i] + minv[i] * (b[i] - ell_dot(A, i, xold));
+  xnew[i] = xold[i] + minv[i] * (b[i] - ell_dot<false>(A, i, xold));
 }
 
 template <typename T>
@@ -266,12 +285,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int32_t* 
   bc[I] = s;
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t* __restrict__ agg,
                                                     const T* __restrict__ xc, T* __restrict__ x) {
   const int64_t i = row_index();
   if (i >= n) return;
-  x[i] = x[i] + xc[agg[i]];
+  x[i] = ld<NT>(x + i) + xc[ld<NT>(agg + i)];
+}
+
+// y += A x for an explicit (smoothed) prolongator in sliced ELL
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void k_spmv_add(int64_t n, EllView<T> A, const T* __restrict__ x,
+                                                     T* __restrict__ y) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  y[i] = ld<NT>(y + i) + ell_dot<NT>(A, i, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,14 +356,15 @@ __global__ __launch_bounds__(kBlock) void k_pad_out(int64_t total, int64_t nl, i
 // CG kernels (float64): fused SpMV + dot, update + dot, and a single-block
 // second-stage reduction that also forms the CG scalars on the device.
 // ---------------------------------------------------------------------------
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __restrict__ a,
                                                  const double* __restrict__ b, const double* __restrict__ c,
                                                  const double* __restrict__ d, double* __restrict__ partial) {
   const int64_t i = row_index();
   double v = 0.0, u = 0.0;
   if (i < n) {
-    v = a[i] * b[i];
-    if (c) u = c[i] * d[i];
+    v = ld<NT>(a + i) * ld<NT>(b + i);
+    if (c) u = ld<NT>(c + i) * ld<NT>(d + i);
   }
   const double sv = block_sum(v);
   __syncthreads();
@@ -346,13 +375,14 @@ __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __rest
   }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> A, const double* __restrict__ p,
                                                      double* __restrict__ q, double* __restrict__ partial) {
   const int64_t i = row_index();
   double v = 0.0;
   if (i < n) {
-    const double qi = ell_dot(A, i, p);
-    q[i] = qi;
+    const double qi = ell_dot<NT>(A, i, p);
+    st<NT>(q + i, qi);
     v = p[i] * qi;
   }
   const double s = block_sum(v);
@@ -363,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> 
 // q = A p_new, with (p_new, q) partials.  p_new of a neighbour is formed on the
 // fly from z and p_old (exactly the value stored for it), so p_new is written
 // to the other buffer of a pair.
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double> A, const double* __restrict__ scal,
                                                        const double* __restrict__ z, const double* __restrict__ pold,
                                                        double* __restrict__ pnew, double* __restrict__ q,
@@ -377,12 +408,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     double acc = 0.0;
 #pragma unroll 4
     for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
-      const int j = A.col[p];
-      acc += A.val[p] * (z[j] + beta * pold[j]);
+      const int j = ld<NT>(A.col + p);
+      acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
     }
     const double pi = z[i] + beta * pold[i];
-    pnew[i] = pi;
-    q[i] = acc;
+    st<NT>(pnew + i, pi);
+    st<NT>(q + i, acc);
     v = pi * acc;
   }
   const double sum = block_sum(v);
@@ -391,6 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
 
 // x += alpha p, r -= alpha q (alpha from the device scalars), partial (r, r);
 // rold (flexible CG) receives the previous r.
+template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ scal,
                                                       const double* __restrict__ p, const double* __restrict__ q,
                                                       double* __restrict__ x, double* __restrict__ r,
@@ -399,10 +431,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* _
   const double alpha = scal[S_ALPHA];
   double v = 0.0;
   if (i < n) {
-    x[i] = x[i] + alpha * p[i];
-    const double ro = r[i];
-    if (rold) rold[i] = ro;
-    const double rn = ro - alpha * q[i];
+    st<NT>(x + i, ld<NT>(x + i) + alpha * ld<NT>(p + i));
+    const double ro = ld<NT>(r + i);
+    if (rold) st<NT>(rold + i, ro);
+    const double rn = ro - alpha * ld<NT>(q + i);
     r[i] = rn;
     v = rn * rn;
   }
@@ -512,77 +544,129 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(int64_t n, const double
 
 #define LAUNCH_OK() (hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP)
 
+// Levels above kRemapMaxBlocks blocks take the streaming (NT) kernels.
+inline bool streamed(unsigned grid) { return grid > kRemapMaxBlocks; }
+
 template <typename T>
 int launch_spmv(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
-  hipLaunchKernelGGL(k_spmv<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  const unsigned g = xcd_grid(A.n);
+  if (streamed(g))
+    hipLaunchKernelGGL((k_spmv<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  else
+    hipLaunchKernelGGL((k_spmv<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
   return LAUNCH_OK();
 }
 
 template <typename T>
 int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r) {
-  hipLaunchKernelGGL(k_residual<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
+  const unsigned g = xcd_grid(A.n);
+  if (streamed(g))
+    hipLaunchKernelGGL((k_residual<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
+  else
+    hipLaunchKernelGGL((k_residual<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
   return LAUNCH_OK();
+}
+
+template <typename T, bool NT>
+void go_first_zero(dim3 gr, hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
+                   T* x, T c, T w, Wt wv) {
+  dim3 bl(kBlock);
+  if (mode == 0 && store)
+    hipLaunchKernelGGL((k_first_zero<T, 0, true, NT>), gr, bl, 0, s, n, minv, b, g, r, x, c, w, wv);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_first_zero<T, 0, false, NT>), gr, bl, 0, s, n, minv, b, g, r, x, c, w, wv);
+  else if (store)
+    hipLaunchKernelGGL((k_first_zero<T, 1, true, NT>), gr, bl, 0, s, n, minv, b, g, r, x, c, w, wv);
+  else
+    hipLaunchKernelGGL((k_first_zero<T, 1, false, NT>), gr, bl, 0, s, n, minv, b, g, r, x, c, w, wv);
 }
 
 template <typename T>
 int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* minv, const T* b, T* g, T* r,
                       T* x, double c, double w, Wt wv) {
-  dim3 gr(xcd_grid(n)), bl(kBlock);
-  if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first_zero<T, 0, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_first_zero<T, 0, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
-  else if (store)
-    hipLaunchKernelGGL((k_first_zero<T, 1, true>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
+  const dim3 gr(xcd_grid(n));
+  if (streamed(gr.x))
+    go_first_zero<T, true>(gr, s, mode, store, n, minv, b, g, r, x, (T)c, (T)w, wv);
   else
-    hipLaunchKernelGGL((k_first_zero<T, 1, false>), gr, bl, 0, s, n, minv, b, g, r, x, (T)c, (T)w, wv);
+    go_first_zero<T, false>(gr, s, mode, store, n, minv, b, g, r, x, (T)c, (T)w, wv);
   return LAUNCH_OK();
+}
+
+template <typename T, bool NT>
+void go_first2_zero(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv,
+                    const T* b, T* gnew, T* r, T* x, T a1, T a2, T a3, T a4, T a5, Wt w1v, Wt w2v) {
+  dim3 bl(kBlock);
+  if (mode == 0 && store)
+    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4, a5,
+                       w1v, w2v);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+                       a5, w1v, w2v);
+  else if (store)
+    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4, a5,
+                       w1v, w2v);
+  else
+    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+                       a5, w1v, w2v);
 }
 
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
                        T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v, Wt w2v) {
-  dim3 gr(xcd_grid(A.n)), bl(kBlock);
-  const T a1 = (T)c1, a2 = (T)alpha, a3 = (T)c, a4 = (T)w1, a5 = (T)w2;
-  if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
-  else if (store)
-    hipLaunchKernelGGL((k_first2_zero<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
+  const dim3 gr(xcd_grid(A.n));
+  if (streamed(gr.x))
+    go_first2_zero<T, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c, (T)w1,
+                            (T)w2, w1v, w2v);
   else
-    hipLaunchKernelGGL((k_first2_zero<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, b, gnew, r, x, a1, a2, a3, a4, a5, w1v, w2v);
+    go_first2_zero<T, false>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c, (T)w1,
+                             (T)w2, w1v, w2v);
   return LAUNCH_OK();
 }
 
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c) {
-  dim3 gr(xcd_grid(A.n)), bl(kBlock);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_first_res<T, 0>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+  const dim3 gr(xcd_grid(A.n)), bl(kBlock);
+  const bool nt = streamed(gr.x);
+  if (mode == 0 && nt)
+    hipLaunchKernelGGL((k_first_res<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_first_res<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+  else if (nt)
+    hipLaunchKernelGGL((k_first_res<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
   else
-    hipLaunchKernelGGL((k_first_res<T, 1>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
+    hipLaunchKernelGGL((k_first_res<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
   return LAUNCH_OK();
+}
+
+template <typename T, bool NT>
+void go_fused(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv, const T* gold,
+              T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv) {
+  dim3 bl(kBlock);
+  if (mode == 0 && store)
+    hipLaunchKernelGGL((k_fused<T, 0, true, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+                       wp_, wv, wpv);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_fused<T, 0, false, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+                       wp_, wv, wpv);
+  else if (store)
+    hipLaunchKernelGGL((k_fused<T, 1, true, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+                       wp_, wv, wpv);
+  else
+    hipLaunchKernelGGL((k_fused<T, 1, false, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+                       wp_, wv, wpv);
 }
 
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
                  const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv) {
-  dim3 gr(xcd_grid(A.n)), bl(kBlock);
-  const T a_ = (T)alpha, c_ = (T)c, w_ = (T)w, wp_ = (T)wprev;
-  if (mode == 0 && store)
-    hipLaunchKernelGGL((k_fused<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
-                       w_, wp_, wv, wpv);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_fused<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
-                       c_, w_, wp_, wv, wpv);
-  else if (store)
-    hipLaunchKernelGGL((k_fused<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_, c_,
-                       w_, wp_, wv, wpv);
+  const dim3 gr(xcd_grid(A.n));
+  if (streamed(gr.x))
+    go_fused<T, true>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
+                      (T)wprev, wv, wpv);
   else
-    hipLaunchKernelGGL((k_fused<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, gold, gnew, rin, rout, x, a_,
-                       c_, w_, wp_, wv, wpv);
+    go_fused<T, false>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
+                       (T)wprev, wv, wpv);
   return LAUNCH_OK();
 }
 
@@ -601,14 +685,28 @@ int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x
 template <typename T>
 int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
                     const T* x, T* tmp, T* bc) {
-  hipLaunchKernelGGL(k_residual<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), b, x, tmp);
+  AMGP_TRY(launch_residual<T>(s, A, b, x, tmp));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, children, (const T*)tmp, bc);
   return LAUNCH_OK();
 }
 
 template <typename T>
 int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T* x) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, agg, xc, x);
+  const unsigned g = xcd_grid(n);
+  if (streamed(g))
+    hipLaunchKernelGGL((k_prolong<T, true>), dim3(g), dim3(kBlock), 0, s, n, agg, xc, x);
+  else
+    hipLaunchKernelGGL((k_prolong<T, false>), dim3(g), dim3(kBlock), 0, s, n, agg, xc, x);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_spmv_add(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
+  const unsigned g = xcd_grid(A.n);
+  if (streamed(g))
+    hipLaunchKernelGGL((k_spmv_add<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  else
+    hipLaunchKernelGGL((k_spmv_add<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
   return LAUNCH_OK();
 }
 
@@ -653,7 +751,10 @@ int launch_pad_out(hipStream_t s, int nbatch, int64_t nl, int64_t np, const doub
 int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
                 double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(n);
-  hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_dot2<true>, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
+  else
+    hipLaunchKernelGGL(k_dot2<false>, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
@@ -661,7 +762,10 @@ int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, cons
 int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
                     unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
-  hipLaunchKernelGGL(k_spmv_dot, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_spmv_dot<true>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
+  else
+    hipLaunchKernelGGL(k_spmv_dot<false>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
@@ -669,7 +773,12 @@ int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
                       double* pnew, double* q, double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
-  hipLaunchKernelGGL(k_spmv_dot_p, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q, partial);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_spmv_dot_p<true>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_spmv_dot_p<false>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
+                       partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
@@ -677,7 +786,10 @@ int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, c
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(n);
-  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_cg_update<true>, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
+  else
+    hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
@@ -721,6 +833,7 @@ int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
   template int launch_jacobi_zero<T>(hipStream_t, int64_t, const T*, const T*, T*);                           \
   template int launch_restrict<T>(hipStream_t, const Ell<T>&, int64_t, const int32_t*, const T*, const T*, T*, T*); \
   template int launch_prolong<T>(hipStream_t, int64_t, const int32_t*, const T*, T*);                         \
+  template int launch_spmv_add<T>(hipStream_t, const Ell<T>&, const T*, T*);                                 \
   template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*, Wt);                                \
   template int launch_copy<T>(hipStream_t, int64_t, const T*, T*);                                           \
   template int launch_fill<T>(hipStream_t, int64_t, T, T*);                                                   \

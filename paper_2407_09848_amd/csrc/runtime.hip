@@ -19,11 +19,15 @@ struct Prec;
 template <>
 struct Prec<double> {
   static const Ell<double>& A(const Level& l) { return l.A64; }
+  static const Ell<double>& P(const Level& l) { return l.P64; }
+  static const Ell<double>& PT(const Level& l) { return l.PT64; }
   static Vecs<double>& v(Level& l) { return l.v64; }
 };
 template <>
 struct Prec<float> {
   static const Ell<float>& A(const Level& l) { return l.A32; }
+  static const Ell<float>& P(const Level& l) { return l.P32; }
+  static const Ell<float>& PT(const Level& l) { return l.PT32; }
   static Vecs<float>& v(Level& l) { return l.v32; }
 };
 
@@ -75,6 +79,10 @@ void release(Handle* h) {
     free_vecs(L.v32, true);
     hipFree(L.agg);
     hipFree(L.children);
+    free_ell(L.P64);
+    free_ell(L.PT64);
+    free_ell(L.P32);
+    free_ell(L.PT32);
   }
   hipFree(h->ainv);
   hipFree(h->cb);
@@ -224,7 +232,40 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
 
 template <typename T>
 int coarse(Handle* h, const T* b, T* x, hipStream_t s) {
+  if (h->coarse_sweeps > 0) return smooth<T>(h, h->nlevels - 1, AMG_L1JAC, h->coarse_sweeps, b, x, true, s);
   return launch_coarse_symv<T>(s, h->nbatch, h->ncl, h->ncp, h->ainv, b, x, h->cpart);
+}
+
+// Transfers between level l and l + 1 (Section 2): b_c = P^T (b - A x) (tmp receives
+// b - A x), x += P x_c, and the plain products y_c = P^T y and y = P y_c used by the
+// adjoint.  P is the 2x2x2 box indicator (children / aggregate gathers) or explicit.
+template <typename T>
+int restrict_res(Handle* h, int l, const T* b, const T* x, T* tmp, T* bc, hipStream_t s) {
+  Level& L = h->lv[l];
+  if (!L.general) return launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, tmp, bc);
+  AMGP_TRY(launch_residual<T>(s, Prec<T>::A(L), b, x, tmp));
+  return launch_spmv<T>(s, Prec<T>::PT(L), tmp, bc);
+}
+
+template <typename T>
+int prolong_add(Handle* h, int l, const T* xc, T* x, hipStream_t s) {
+  Level& L = h->lv[l];
+  if (!L.general) return launch_prolong<T>(s, L.n, L.agg, xc, x);
+  return launch_spmv_add<T>(s, Prec<T>::P(L), xc, x);
+}
+
+template <typename T>
+int restrict_apply(Handle* h, int l, const T* y, T* yc, hipStream_t s) {
+  Level& L = h->lv[l];
+  if (!L.general) return launch_restrict_sum<T>(s, L.nc, L.children, y, yc);
+  return launch_spmv<T>(s, Prec<T>::PT(L), y, yc);
+}
+
+template <typename T>
+int prolong_set(Handle* h, int l, const T* yc, T* y, hipStream_t s) {
+  Level& L = h->lv[l];
+  if (!L.general) return launch_prolong_set<T>(s, L.n, L.agg, yc, y);
+  return launch_spmv<T>(s, Prec<T>::P(L), yc, y);
 }
 
 // V-cycle of eq. (amg) from level l: x = B_l b.
@@ -234,9 +275,9 @@ int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s) {
   Level& L = h->lv[l];
   Vecs<T>& vc = Prec<T>::v(h->lv[l + 1]);
   AMGP_TRY(smooth<T>(h, l, kind, k, b, x, true, s));
-  AMGP_TRY(launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, Prec<T>::v(L).r, vc.b));
+  AMGP_TRY(restrict_res<T>(h, l, b, x, Prec<T>::v(L).r, vc.b, s));
   AMGP_TRY(vcycle<T>(h, l + 1, kind, k, vc.b, vc.x, s));
-  AMGP_TRY(launch_prolong<T>(s, L.n, L.agg, vc.x, x));
+  AMGP_TRY(prolong_add<T>(h, l, vc.x, x, s));
   return smooth<T>(h, l, kind, k, b, x, false, s);
 }
 
@@ -370,9 +411,9 @@ int vcycle_fwd_ck(Handle* h, int l, int k, const T* b, T* x, T* ck, hipStream_t 
   T* ck_post = ck_pre + L.n;
   AMGP_TRY(launch_copy<T>(s, L.n, b, ck_pre));
   AMGP_TRY(smooth<T>(h, l, AMG_OPTCHEB4, k, b, x, true, s));
-  AMGP_TRY(launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, Prec<T>::v(L).r, vc.b));
+  AMGP_TRY(restrict_res<T>(h, l, b, x, Prec<T>::v(L).r, vc.b, s));
   AMGP_TRY(vcycle_fwd_ck<T>(h, l + 1, k, vc.b, vc.x, ck, s));
-  AMGP_TRY(launch_prolong<T>(s, L.n, L.agg, vc.x, x));
+  AMGP_TRY(prolong_add<T>(h, l, vc.x, x, s));
   return smooth<T>(h, l, AMG_OPTCHEB4, k, b, x, false, s, ck_post);
 }
 
@@ -418,10 +459,10 @@ int vcycle_bwd_rec(Handle* h, int l, int k, const T* xo_bar, T* b_bar, const T* 
   AMGP_TRY(smooth_adjoint<T>(h, l, k, xo_bar, a.u, ck_post, gbeta, s));
   AMGP_TRY(launch_residual<T>(s, A, xo_bar, a.u, a.xmid));  // x_mid_bar = x_out_bar - A u
   // x_mid = x_pre + P x_c
-  AMGP_TRY(launch_restrict_sum<T>(s, L.nc, L.children, a.xmid, ac.xin));
+  AMGP_TRY(restrict_apply<T>(h, l, a.xmid, ac.xin, s));
   AMGP_TRY(vcycle_bwd_rec<T>(h, l + 1, k, ac.xin, ac.bout, ck, gbeta, s));
   // b_c = P^T (b - A x_pre)
-  AMGP_TRY(launch_prolong_set<T>(s, L.n, L.agg, ac.bout, a.res));
+  AMGP_TRY(prolong_set<T>(h, l, ac.bout, a.res, s));
   AMGP_TRY(launch_residual<T>(s, A, a.xmid, a.res, a.xpre));  // x_pre_bar = x_mid_bar - A res_bar
   // pre-smoothing from zero: x_pre = Q b
   AMGP_TRY(smooth_adjoint<T>(h, l, k, a.xpre, b_bar, ck_pre, gbeta, s));
@@ -485,11 +526,46 @@ __global__ void k_round_vec(int64_t n, const double* __restrict__ a, float* __re
   if (i < n) b[i] = (float)a[i];
 }
 
+// Transfer operators and Galerkin product of level L with an explicit prolongator:
+// P = P_hat or (I - omega D^{-1} A) P_hat, P^T, A_c = P^T (A P), and the sliced-ELL copies of P, P^T.
+struct CsrHold {
+  Csr c;
+  ~CsrHold() { free_csr(c); }
+};
+
+int general_level(Handle* h, hipStream_t s, Level& L, Level* C) {
+  Csr A;
+  A.m = L.n;
+  A.ncols = L.n;
+  A.nnz = L.nnz;
+  A.ptr = L.csr_ptr;
+  A.col = L.csr_col;
+  A.val = L.csr_val;
+  CsrHold P, PT, Ac;
+  if (h->smoothed)
+    AMGP_TRY(smoothed_prolongator(s, A, h->nbatch, L.agg, L.nc, &P.c, h->dflag));
+  else
+    AMGP_TRY(tentative_prolongator(s, L.n, L.nc, L.agg, &P.c));
+  AMGP_TRY(transpose(s, P.c, &PT.c));
+  AMGP_TRY(galerkin_general(s, A, P.c, PT.c, &Ac.c, h->dflag));
+  AMGP_TRY(build_ell64(s, P.c.m, P.c.ptr, P.c.col, P.c.val, &L.P64, P.c.ncols));
+  AMGP_TRY(build_ell64(s, PT.c.m, PT.c.ptr, PT.c.col, PT.c.val, &L.PT64, PT.c.ncols));
+  C->csr_ptr = Ac.c.ptr;
+  C->csr_col = Ac.c.col;
+  C->csr_val = Ac.c.val;
+  C->nnz = Ac.c.nnz;
+  Ac.c = Csr();  // now owned by the level
+  return AMG_OK;
+}
+
 int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const double* val,
           const amg_opts* o, hipStream_t s) {
   h->nbatch = o->nbatch > 0 ? o->nbatch : 1;
   h->max_coarse = o->max_coarse > 0 ? o->max_coarse : 4096;
   h->precision = o->precision;
+  h->agg_edge = o->agg_edge > 0 ? o->agg_edge : 2;
+  h->smoothed = o->smoothed != 0;
+  h->coarse_sweeps = o->coarse_sweeps;
   {
     const char* e = std::getenv("AMGP_NO_GRAPH");
     h->use_graphs = !(e && e[0] == '1');
@@ -524,25 +600,31 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     const int64_t per = L.n / h->nbatch;
     if (per <= h->max_coarse) break;
     int cx, cy, cz;
-    const int64_t nc = (int64_t)(L.nx == 1 ? 1 : (L.nx + 1) / 2) * (L.ny == 1 ? 1 : (L.ny + 1) / 2) *
-                       (L.nz == 1 ? 1 : (L.nz + 1) / 2) * h->nbatch;
+    const int e = h->agg_edge;
+    auto cdim = [e](int v) { return v == 1 ? 1 : (v + e - 1) / e; };
+    const int64_t nc = (int64_t)cdim(L.nx) * cdim(L.ny) * cdim(L.nz) * h->nbatch;
     if (nc >= L.n) break;
     L.nc = nc;
+    L.general = h->smoothed || e != 2;
     AMGP_TRY(dalloc(&L.agg, L.n));
-    AMGP_TRY(dalloc(&L.children, nc * kMaxChildren));
-    AMGP_TRY(launch_aggregates(s, L.nx, L.ny, L.nz, h->nbatch, L.agg, L.children, &cx, &cy, &cz));
+    if (!L.general) AMGP_TRY(dalloc(&L.children, nc * kMaxChildren));
+    AMGP_TRY(launch_aggregates(s, L.nx, L.ny, L.nz, h->nbatch, e, L.agg, L.children, &cx, &cy, &cz));
     Level C;
     C.n = nc;
     C.nx = cx;
     C.ny = cy;
     C.nz = cz;
-    AMGP_TRY(galerkin(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, L.agg, nc, L.children, &C.csr_ptr, &C.csr_col,
-                      &C.csr_val, &C.nnz, h->dflag));
+    if (!L.general) {
+      AMGP_TRY(galerkin(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, L.agg, nc, L.children, &C.csr_ptr, &C.csr_col,
+                        &C.csr_val, &C.nnz, h->dflag));
+    } else {
+      AMGP_TRY(general_level(h, s, L, &C));
+    }
     h->lv.push_back(C);
   }
   h->nlevels = (int)h->lv.size();
-  // coarsest level: dense inverse through the Cholesky factor
-  {
+  // coarsest level: dense inverse through the Cholesky factor (unless it is smoothed instead)
+  if (h->coarse_sweeps <= 0) {
     Level& L = h->lv.back();
     h->ncl = L.n / h->nbatch;
     h->ncp = (h->ncl + kDenseTile - 1) / kDenseTile * kDenseTile;
@@ -562,6 +644,10 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     AMGP_TRY(alloc_vecs(L.v64, L.n, l > 0));
     if (h->precision == AMG_FP32) {
       AMGP_TRY(build_ell32(s, L.A64, &L.A32));
+      if (L.general) {
+        AMGP_TRY(build_ell32(s, L.P64, &L.P32));
+        AMGP_TRY(build_ell32(s, L.PT64, &L.PT32));
+      }
       AMGP_TRY(alloc_vecs(L.v32, L.n, true));
       AMGP_TRY(dalloc(&L.v32.minv, L.n));
       hipLaunchKernelGGL(k_round_vec, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.v64.minv, L.v32.minv);
@@ -604,9 +690,15 @@ int fetch_scalars(Handle* h, hipStream_t s) {
   return AMG_OK;
 }
 
+// poly_only: the preconditioner is the level-0 smoother alone, z = p_k(M^{-1}A) M^{-1} r from z = 0
+// (the polynomial-preconditioning experiment of the remark after Fig. boundcomparison); otherwise
+// the V-cycle of eq. (amg).
 int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double rtol, int maxit, bool flex,
-        int* iters, double* relres, double* hist, hipStream_t s) {
+        bool poly_only, int* iters, double* relres, double* hist, hipStream_t s) {
   const int64_t n = h->lv[0].n;
+  auto precond = [&](const double* rr, double* zz) {
+    return poly_only ? smooth<double>(h, 0, kind, k, rr, zz, true, s) : vcycle_run(h, kind, k, rr, zz, s);
+  };
   const Ell<double>& A = h->lv[0].A64;
   double *r = h->cg_r, *z = h->cg_z, *p = h->cg_p, *q = h->cg_q, *rold = flex ? h->cg_rold : nullptr;
   const int* hflag = reinterpret_cast<const int*>(h->hscal + S_NSCAL);
@@ -637,7 +729,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   if (hist) hist[0] = rel0;
   *relres = rel0;
   if (rel0 <= rtol) return AMG_OK;
-  AMGP_TRY(vcycle_run(h, kind, k, r, z, s));
+  AMGP_TRY(precond(r, z));
   AMGP_TRY(sum_dot(h, s, RED_RZ0, r, z, nullptr, nullptr, n));  // also sets beta = 0: p_1 = z_0
   double* pold = h->cg_p2;
   AMGP_TRY(launch_fill<double>(s, n, 0.0, pold));
@@ -656,7 +748,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
     if (hist) hist[it] = rel;
     if (rel <= rtol) return AMG_OK;
     if (it == maxit) break;
-    AMGP_TRY(vcycle_run(h, kind, k, r, z, s));
+    AMGP_TRY(precond(r, z));
     if (flex)
       AMGP_TRY(sum_dot(h, s, RED_BETA_FLEX, r, z, rold, z, n));
     else
@@ -689,6 +781,9 @@ int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d
   if (o.nx < 1 || o.ny < 1 || o.nz < 1 || o.max_coarse < 0) return AMG_EINVAL;
   if ((int64_t)o.nx * o.ny * o.nz * nb != n) return AMG_EINVAL;
   if (o.precision != AMG_FP64 && o.precision != AMG_FP32) return AMG_EINVAL;
+  if (o.agg_edge < 0 || o.agg_edge == 1 || o.agg_edge > 4) return AMG_EINVAL;
+  if (o.smoothed != 0 && o.smoothed != 1) return AMG_EINVAL;
+  if (o.coarse_sweeps < 0 || o.coarse_sweeps > 1000) return AMG_EINVAL;
   amg_handle* h = new (std::nothrow) amg_handle;
   if (!h) return AMG_ENOMEM;
   const int rc = amgp::setup(&h->impl, n, nnz, d_row_ptr, d_col, d_val, &o, (hipStream_t)stream);
@@ -787,13 +882,12 @@ int amg_restrict_residual(amg_handle* h, int level, const double* d_b, const dou
                           void* stream) {
   if (!h || !d_b || !d_x || !d_bc || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;
   amgp::Level& L = h->impl.lv[level];
-  return amgp::launch_restrict<double>((hipStream_t)stream, L.A64, L.nc, L.children, d_b, d_x, L.v64.r, d_bc);
+  return amgp::restrict_res<double>(&h->impl, level, d_b, d_x, L.v64.r, d_bc, (hipStream_t)stream);
 }
 
 int amg_prolong_add(amg_handle* h, int level, const double* d_xc, double* d_x, void* stream) {
   if (!h || !d_xc || !d_x || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;
-  const amgp::Level& L = h->impl.lv[level];
-  return amgp::launch_prolong<double>((hipStream_t)stream, L.n, L.agg, d_xc, d_x);
+  return amgp::prolong_add<double>(&h->impl, level, d_xc, d_x, (hipStream_t)stream);
 }
 
 int amg_coarse_solve(amg_handle* h, const double* d_b, double* d_x, void* stream) {
@@ -811,8 +905,17 @@ int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_
               int maxit, int flexible, int* h_iters, double* h_relres, double* h_hist, void* stream) {
   if (!h || !d_b || !d_x || !h_iters || !h_relres || maxit < 1 || !(rtol >= 0.0)) return AMG_EINVAL;
   AMGP_TRY(amgp::check_kind_degree(kind, degree));
-  return amgp::pcg(&h->impl, kind, degree, d_b, d_x, x_is_zero != 0, rtol, maxit, flexible != 0, h_iters, h_relres,
-                   h_hist, (hipStream_t)stream);
+  return amgp::pcg(&h->impl, kind, degree, d_b, d_x, x_is_zero != 0, rtol, maxit, flexible != 0, false, h_iters,
+                   h_relres, h_hist, (hipStream_t)stream);
+}
+
+int pcg_solve_smoother(amg_handle* h, int kind, int degree, const double* d_b, double* d_x, int x_is_zero,
+                       double rtol, int maxit, int flexible, int* h_iters, double* h_relres, double* h_hist,
+                       void* stream) {
+  if (!h || !d_b || !d_x || !h_iters || !h_relres || maxit < 1 || !(rtol >= 0.0)) return AMG_EINVAL;
+  AMGP_TRY(amgp::check_kind_degree(kind, degree));
+  return amgp::pcg(&h->impl, kind, degree, d_b, d_x, x_is_zero != 0, rtol, maxit, flexible != 0, true, h_iters,
+                   h_relres, h_hist, (hipStream_t)stream);
 }
 
 int amg_ckpt_bytes(const amg_handle* h, int64_t* h_bytes) {

@@ -31,7 +31,7 @@ def nan_vec(n):
 
 
 @contextlib.contextmanager
-def hierarchy(A, nbatch=1, max_coarse=4096, precision=0):
+def hierarchy(A, nbatch=1, max_coarse=4096, precision=0, **opts):
     import paper_2407_09848_amd as amg
     torch = torch_cuda()
     nx, ny, nz = A.grid
@@ -39,7 +39,7 @@ def hierarchy(A, nbatch=1, max_coarse=4096, precision=0):
     rp = dev(A.row_ptr.astype(np.int32))
     cl = dev(A.col.astype(np.int32))
     vl = dev(A.val.astype(np.float64))
-    h = amg.amg_setup(rp, cl, vl, nx, ny, nz_per, nbatch, max_coarse, precision)
+    h = amg.amg_setup(rp, cl, vl, nx, ny, nz_per, nbatch, max_coarse, precision, **opts)
     torch.cuda.synchronize()
     try:
         yield h

@@ -35,6 +35,8 @@ __all__ = [
     "SEED_MLP",
     "mlp_init",
     "config4_sigmas",
+    "qdq_dense",
+    "anisotropy2d_q1",
 ]
 
 # Seed bases: b uses default_rng(SEED_RHS + config number), the Gaussian
@@ -317,3 +319,111 @@ def mlp_init(seed: int = SEED_MLP):
         else:
             parts.append(np.zeros(shape))
     return np.concatenate(parts)
+
+
+def qdq_dense(N: int, spectrum: str):
+    """Dense SPD test matrix A = Q D Q^T of the polynomial-preconditioning experiment
+    (the remark after Fig. boundcomparison, Fig. better-than-optimal).
+
+    Q holds the orthonormal eigenvectors of the 1D second-difference matrix
+    tridiag(-1, 2, -1) of order N, the discrete sines
+    Q[i, j] = sqrt(2/(N+1)) sin((i+1)(j+1) pi/(N+1)).  D (N even) is one of
+      'equispaced': N points equally spaced in [1/N, 1];
+      'clustered':  1 - logspace(-8, -1, N/2) followed by logspace(-8, -1, N/2),
+                    eigenvalues accumulating at both ends of (0, 1);
+      'gap':        logspace(-8, -1, N/2) followed by N/2 points logarithmically
+                    spaced from 10 down to pi (the MATLAB meaning of logspace(1, pi, m)).
+    The right-hand side is b = A 1.  Returns (CSR with full rows, b, d).
+    """
+    if N < 2 or N % 2:
+        raise ValueError("N must be even and >= 2")
+    m = N // 2
+    if spectrum == "equispaced":
+        d = np.linspace(1.0 / N, 1.0, N)
+    elif spectrum == "clustered":
+        lo = np.logspace(-8, -1, m)
+        d = np.concatenate([1.0 - lo, lo])
+    elif spectrum == "gap":
+        d = np.concatenate([np.logspace(-8, -1, m), 10.0 ** np.linspace(1.0, np.log10(np.pi), m)])
+    else:
+        raise ValueError(spectrum)
+    idx = np.arange(1, N + 1, dtype=np.float64)
+    Q = np.sqrt(2.0 / (N + 1)) * np.sin(np.outer(idx, idx) * np.pi / (N + 1))
+    A = (Q * d[None, :]) @ Q.T
+    A = 0.5 * (A + A.T)  # exactly symmetric
+    b = A @ np.ones(N)
+    row_ptr = (np.arange(N + 1, dtype=np.int64) * N).astype(np.int32)
+    col = np.tile(np.arange(N, dtype=np.int32), N)
+    return CSR(n=N, row_ptr=row_ptr, col=col, val=A.ravel().copy(), grid=(N, 1, 1)), b, d
+
+
+def _q1_element_2d(kxx: float, kxy: float, kyy: float) -> np.ndarray:
+    """Stiffness of one bilinear square element for the constant tensor K (mesh-size free in 2D),
+    exact by 2x2 Gauss quadrature.  Local node (a, b) = (x offset, y offset) has index a + 2b."""
+    g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
+    Ke = np.zeros((4, 4))
+    K = np.array([[kxx, kxy], [kxy, kyy]])
+    for xi in g:
+        for eta in g:
+            grads = []
+            for b_ in (0, 1):
+                for a_ in (0, 1):
+                    fx = xi if a_ else 1.0 - xi
+                    fy = eta if b_ else 1.0 - eta
+                    dfx = 1.0 if a_ else -1.0
+                    dfy = 1.0 if b_ else -1.0
+                    grads.append((dfx * fy, fx * dfy))
+            G = np.array(grads)  # (4, 2)
+            Ke += 0.25 * G @ K @ G.T
+    return 0.5 * (Ke + Ke.T)  # exactly symmetric, so the assembled matrix is too
+
+
+def anisotropy2d_q1(N: int, eps: float = 100.0, theta: float = np.pi / 6):
+    """Anisotropic 2D thermal problem of Section 4 ("Anisotropy 2D"), Q1 finite elements.
+
+    Domain [-1, 1]^2 split into N x N square elements; conductivity
+    K = R(theta) diag(1, eps) R(theta)^T; homogeneous Dirichlet condition on the
+    face y = -1 (those nodes are eliminated), natural (Neumann) conditions on the
+    other three faces; load f(x, y) = exp(-100 (x^2 + y^2)) integrated against
+    the basis functions with 2x2 Gauss points per element.
+    Unknowns: the (N+1) x N nodes with y > -1, ordered i + (N+1) j (x fastest),
+    so grid = (N+1, N, 1).  Each row has the 9-point pattern of its node.
+    Returns (CSR, b).
+    """
+    c, s_ = np.cos(theta), np.sin(theta)
+    kxx = c * c + eps * s_ * s_
+    kyy = s_ * s_ + eps * c * c
+    kxy = (1.0 - eps) * s_ * c
+    Ke = _q1_element_2d(kxx, kxy, kyy)
+    nxn, nyn = N + 1, N + 1  # all nodes, including y = -1
+    I = np.arange(nxn)[None, :]
+    J = np.arange(nyn)[:, None]
+    offs, vals = [], []
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            v = np.zeros((nyn, nxn))
+            for ea in (-1, 0):
+                for eb in (-1, 0):
+                    a_, b_ = -ea, -eb  # local position of the row node in element (i+ea, j+eb)
+                    a2, b2 = a_ + dx, b_ + dy
+                    if not (0 <= a2 <= 1 and 0 <= b2 <= 1):
+                        continue
+                    ok = (I + ea >= 0) & (I + ea <= N - 1) & (J + eb >= 0) & (J + eb <= N - 1)
+                    v += np.where(ok, Ke[a_ + 2 * b_, a2 + 2 * b2], 0.0)
+            offs.append((dx, dy, 0))
+            vals.append(v[1:][None, :, :])  # drop the Dirichlet row y = -1
+    A = stencil_csr((nxn, N, 1), offs, vals)
+    # load vector
+    h = 2.0 / N
+    g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
+    x0 = -1.0 + h * np.arange(N)
+    F = np.zeros((nyn, nxn))
+    for xi in g:
+        for eta in g:
+            fq = np.exp(-100.0 * ((x0[None, :] + h * xi) ** 2 + (x0[:, None] + h * eta) ** 2)) * (h * h / 4.0)
+            for b_ in (0, 1):
+                for a_ in (0, 1):
+                    phi = (xi if a_ else 1.0 - xi) * (eta if b_ else 1.0 - eta)
+                    F[b_:b_ + N, a_:a_ + N] += phi * fq
+    b = F[1:].ravel().copy()
+    return A, b
