@@ -95,10 +95,14 @@ struct Csr {
 constexpr double kDropTau = 1.4210854715202004e-14;  // 2^-46
 
 // A captured V-cycle (one launch sequence for a given kind, degree and r/z buffers).
+// mode: -1 for a bare V-cycle, else the reduction that follows the preconditioner
+// (RED_RZ0 / RED_BETA / RED_BETA_FLEX); poly: the smoother alone instead of the V-cycle.
 struct GraphEntry {
-  int kind, k;
+  int kind, k, mode;
+  bool poly;
   const void* r;
   void* z;
+  const void* aux;
   hipGraphExec_t exec;
 };
 
@@ -146,6 +150,9 @@ struct Handle {
   double* partial = nullptr;  // 2 * maxblocks
   double* scal = nullptr;     // device scalars
   double* hscal = nullptr;    // pinned host mirror
+  double* hpub = nullptr;     // mapped host memory the (r, r) reduction publishes to: rr, breakdown, nan
+  double* dpub = nullptr;     // its device address
+  hipEvent_t ev = nullptr;    // end of a CG update (the host waits on it)
   int* dflag = nullptr;       // device error flags
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr, *cg_q = nullptr, *cg_rold = nullptr;
   double *tmp64 = nullptr;    // level-0 scratch (n0)
@@ -234,7 +241,9 @@ int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, c
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks);
 int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p);
-int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag);
+// pub (optional, RED_RR): receives (r, r) and the breakdown / NaN flags, for the host
+int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag,
+                  double* pub = nullptr);
 enum ReduceMode { RED_BB = 0, RED_RZ0, RED_ALPHA, RED_RR, RED_BETA, RED_BETA_FLEX };
 int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag);
 

@@ -481,7 +481,8 @@ __global__ __launch_bounds__(1024) void k_reduce_chunks(unsigned nb, int two, co
 }
 
 __global__ __launch_bounds__(1024) void k_reduce(int mode, unsigned nb, const double* __restrict__ partial,
-                                                 double* __restrict__ scal, int* __restrict__ flag) {
+                                                 double* __restrict__ scal, int* __restrict__ flag,
+                                                 double* __restrict__ pub) {
   __shared__ double sm[2][1024 / kWave];
   const bool two = (mode == RED_BETA_FLEX);
   double v = 0.0, u = 0.0;
@@ -520,6 +521,11 @@ __global__ __launch_bounds__(1024) void k_reduce(int mode, unsigned nb, const do
     case RED_RR:
       scal[S_RR] = s;
       if (!(s == s) || s > 1.0e300) flag[F_NAN] = 1;
+      if (pub) {
+        pub[0] = s;
+        pub[1] = (double)flag[F_BREAKDOWN];
+        pub[2] = (double)flag[F_NAN];
+      }
       break;
     case RED_BETA:
       scal[S_BETA] = s / scal[S_RZ];
@@ -799,16 +805,17 @@ int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double
   return LAUNCH_OK();
 }
 
-int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag) {
+int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag,
+                  double* pub) {
   constexpr unsigned kChunks = 64;
   if (nblocks > 16 * 1024) {
     // long lists: 64 blocks sum contiguous chunks into the tail of the partial buffer, then one block
     double* mid = const_cast<double*>(partial) + 2 * (size_t)nblocks;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(kChunks), dim3(1024), 0, s, nblocks, mode == RED_BETA_FLEX ? 1 : 0,
                        partial, mid);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, mode, kChunks, (const double*)mid, scal, flag);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, mode, kChunks, (const double*)mid, scal, flag, pub);
   } else {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, mode, nblocks, partial, scal, flag);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, mode, nblocks, partial, scal, flag, pub);
   }
   return LAUNCH_OK();
 }

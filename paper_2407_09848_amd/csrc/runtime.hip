@@ -92,6 +92,8 @@ void release(Handle* h) {
   hipFree(h->scal);
   hipFree(h->dflag);
   if (h->hscal) hipHostFree(h->hscal);
+  if (h->hpub) hipHostFree(h->hpub);
+  if (h->ev) hipEventDestroy(h->ev);
   hipFree(h->cg_r);
   hipFree(h->cg_z);
   hipFree(h->cg_p);
@@ -296,17 +298,21 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
 // caller's stream.  The coarse levels are launch-latency bound; a graph
 // removes the per-launch host overhead.  The kernel arguments (including the
 // beta weights) are baked in, so changing beta drops the cached graphs.
-int vcycle_run(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s) {
-  if (!h->use_graphs) return vcycle_top(h, kind, k, r, z, s);
+// Runs body(stream) as a HIP graph cached under `key`: captured on the handle's own
+// stream the first time, replayed on the caller's stream afterwards.
+template <typename F>
+int run_graph(Handle* h, const GraphEntry& key, hipStream_t s, F&& body) {
+  if (!h->use_graphs) return body(s);
   for (auto& g : h->graphs)
-    if (g.kind == kind && g.k == k && g.r == r && g.z == z) {
+    if (g.kind == key.kind && g.k == key.k && g.mode == key.mode && g.poly == key.poly && g.r == key.r &&
+        g.z == key.z && g.aux == key.aux) {
       AMGP_HIP(hipGraphLaunch(g.exec, s));
       return AMG_OK;
     }
   if (h->graphs.size() >= 32) drop_graphs(h);
   if (!h->cap) AMGP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   AMGP_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
-  const int rc = vcycle_top(h, kind, k, r, z, h->cap);
+  const int rc = body(h->cap);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap, &graph);
   if (rc != AMG_OK || e != hipSuccess) {
@@ -317,9 +323,16 @@ int vcycle_run(Handle* h, int kind, int k, const double* r, double* z, hipStream
   const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (ei != hipSuccess) return AMG_EHIP;
-  h->graphs.push_back(GraphEntry{kind, k, r, z, exec});
+  GraphEntry g = key;
+  g.exec = exec;
+  h->graphs.push_back(g);
   AMGP_HIP(hipGraphLaunch(exec, s));
   return AMG_OK;
+}
+
+int vcycle_run(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s) {
+  const GraphEntry key{kind, k, -1, false, r, z, nullptr, nullptr};
+  return run_graph(h, key, s, [&](hipStream_t cs) { return vcycle_top(h, kind, k, r, z, cs); });
 }
 
 // ---------------------------------------------------------------------------
@@ -660,6 +673,11 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   AMGP_TRY(dalloc(&h->partial, 2 * maxblocks + 2 * 64));  // + the middle-stage sums of long lists
   AMGP_TRY(dalloc(&h->scal, S_NSCAL));
   if (hipHostMalloc((void**)&h->hscal, sizeof(double) * (S_NSCAL + F_NFLAG)) != hipSuccess) return AMG_ENOMEM;
+  if (hipHostMalloc((void**)&h->hpub, sizeof(double) * 4, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return AMG_ENOMEM;
+  AMGP_HIP(hipHostGetDevicePointer((void**)&h->dpub, h->hpub, 0));
+  AMGP_HIP(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
   AMGP_TRY(dalloc(&h->cg_r, n0));
   AMGP_TRY(dalloc(&h->cg_z, n0));
   AMGP_TRY(dalloc(&h->cg_p, n0));
@@ -690,15 +708,28 @@ int fetch_scalars(Handle* h, hipStream_t s) {
   return AMG_OK;
 }
 
-// poly_only: the preconditioner is the level-0 smoother alone, z = p_k(M^{-1}A) M^{-1} r from z = 0
-// (the polynomial-preconditioning experiment of the remark after Fig. boundcomparison); otherwise
-// the V-cycle of eq. (amg).
+// z = B r followed by the reduction `mode` of (r, z) (and (r_old, z) for the flexible beta),
+// captured together as one graph.  B is the V-cycle, or with poly the level-0 smoother
+// alone from z = 0 (the polynomial preconditioning of the remark after Fig. boundcomparison).
+int precond_dot(Handle* h, int kind, int k, bool poly, int mode, const double* r, double* z, const double* rold,
+                hipStream_t s) {
+  const int64_t n = h->lv[0].n;
+  const GraphEntry key{kind, k, mode, poly, r, z, rold, nullptr};
+  return run_graph(h, key, s, [&](hipStream_t cs) {
+    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs) : vcycle_top(h, kind, k, r, z, cs));
+    if (mode == RED_BETA_FLEX) return sum_dot(h, cs, mode, r, z, rold, z, n);
+    return sum_dot(h, cs, mode, r, z, nullptr, nullptr, n);
+  });
+}
+
+// Preconditioned CG.  Each iteration's update publishes (r, r) and the error flags to mapped
+// host memory; while the host waits for them, the next preconditioner application is
+// already enqueued (it reads r and writes only the handle's workspace), so the GPU does not
+// idle across the convergence test.  When the iteration is predicted to converge (from the
+// last residual reduction rate) the next application is not started ahead.
 int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double rtol, int maxit, bool flex,
         bool poly_only, int* iters, double* relres, double* hist, hipStream_t s) {
   const int64_t n = h->lv[0].n;
-  auto precond = [&](const double* rr, double* zz) {
-    return poly_only ? smooth<double>(h, 0, kind, k, rr, zz, true, s) : vcycle_run(h, kind, k, rr, zz, s);
-  };
   const Ell<double>& A = h->lv[0].A64;
   double *r = h->cg_r, *z = h->cg_z, *p = h->cg_p, *q = h->cg_q, *rold = flex ? h->cg_rold : nullptr;
   const int* hflag = reinterpret_cast<const int*>(h->hscal + S_NSCAL);
@@ -729,30 +760,36 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   if (hist) hist[0] = rel0;
   *relres = rel0;
   if (rel0 <= rtol) return AMG_OK;
-  AMGP_TRY(precond(r, z));
-  AMGP_TRY(sum_dot(h, s, RED_RZ0, r, z, nullptr, nullptr, n));  // also sets beta = 0: p_1 = z_0
+  AMGP_TRY(precond_dot(h, kind, k, poly_only, RED_RZ0, r, z, nullptr, s));  // also beta = 0: p_1 = z_0
   double* pold = h->cg_p2;
   AMGP_TRY(launch_fill<double>(s, n, 0.0, pold));
+  const int next_mode = flex ? RED_BETA_FLEX : RED_BETA;
+  double rel_prev = rel0, rate = 1.0;
   for (int it = 1; it <= maxit; ++it) {
     unsigned nb = 0;
     AMGP_TRY(launch_spmv_dot_p(s, A, h->scal, z, pold, p, q, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_ALPHA, nb, h->partial, h->scal, h->dflag));
     AMGP_TRY(launch_cg_update(s, n, h->scal, p, q, x, r, rold, h->partial, &nb));
-    AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag));
-    AMGP_TRY(fetch_scalars(h, s));
+    AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag, h->dpub));
+    AMGP_HIP(hipEventRecord(h->ev, s));
+    const bool ahead = it < maxit && rel_prev * rate > 2.0 * rtol;
+    if (ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s));
+    AMGP_HIP(hipEventSynchronize(h->ev));
     *iters = it;
-    if (hflag[F_BREAKDOWN]) return AMG_EBREAKDOWN;
-    if (hflag[F_NAN]) return AMG_ENAN;
-    const double rel = std::sqrt(h->hscal[S_RR]) / bnorm;
+    const double rr = h->hpub[0];
+    const bool breakdown = h->hpub[1] != 0.0, nan = h->hpub[2] != 0.0;
+    const double rel = std::sqrt(rr) / bnorm;
     *relres = rel;
     if (hist) hist[it] = rel;
-    if (rel <= rtol) return AMG_OK;
-    if (it == maxit) break;
-    AMGP_TRY(precond(r, z));
-    if (flex)
-      AMGP_TRY(sum_dot(h, s, RED_BETA_FLEX, r, z, rold, z, n));
-    else
-      AMGP_TRY(sum_dot(h, s, RED_BETA, r, z, nullptr, nullptr, n));
+    if (breakdown || nan || rel <= rtol || it == maxit) {
+      AMGP_HIP(hipStreamSynchronize(s));
+      if (breakdown) return AMG_EBREAKDOWN;
+      if (nan) return AMG_ENAN;
+      return rel <= rtol ? AMG_OK : AMG_NOT_CONVERGED;
+    }
+    if (!ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s));
+    rate = rel / rel_prev;
+    rel_prev = rel;
     std::swap(p, pold);  // the next iteration forms p = z + beta pold inside its SpMV
   }
   return AMG_NOT_CONVERGED;
