@@ -140,9 +140,7 @@ struct Handle {
   // coarsest level: dense inverse per problem, padded to ncp
   int64_t ncl = 0;   // rows per problem on the coarsest level
   int64_t ncp = 0;   // padded
-  double* ainv = nullptr;  // [nbatch][ncp][ncp]
-  double* cb = nullptr;    // [nbatch * ncp] padded coarse rhs
-  double* cx = nullptr;    // [nbatch * ncp] padded coarse solution
+  double* ainv = nullptr;  // [nbatch][nb(nb+1)/2][64][64]: lower 64x64 blocks of A_L^{-1}, packed (nb = ncp/64)
   double* cpart = nullptr; // [nbatch][ncp/64][ncp/64][64] partial products of the blocked symmetric solve
   // beta weights: [level][degree][j]
   std::vector<double> beta;  // size nlevels * (AMG_MAX_DEGREE+1) * AMG_MAX_DEGREE
@@ -225,11 +223,6 @@ template <typename T>
 int launch_fill(hipStream_t s, int64_t n, T v, T* y);
 template <typename Tin, typename Tout>
 int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y);
-// coarse rhs gather/scatter between level vectors and the padded dense layout
-template <typename T>
-int launch_pad_in(hipStream_t s, int nbatch, int64_t nl, int64_t np, const T* b, double* out);
-template <typename T>
-int launch_pad_out(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* in, T* x);
 // CG (float64)
 int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
                 double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
@@ -305,7 +298,8 @@ void free_ell(Ell<float>& e);
 // ---- dense kernels (kernels_dense.hip) ----
 // In place: dense[nbatch][np][np] (SPD, lower part used) -> inverse A^{-1}, full symmetric.
 int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np, double* dense, int* flag);
-int launch_coarse_gemv(hipStream_t s, int nbatch, int64_t np, const double* ainv, const double* b, double* x);
+// copy the lower 64x64 blocks of each np x np matrix into contiguous tiles (tile J(J+1)/2 + I = block (J, I))
+int pack_lower_tiles(hipStream_t s, int nbatch, int64_t np, const double* dense, double** packed);
 // x = A^{-1} b from the lower blocks of the symmetric inverse; part holds nbatch * (np/64)^2 * 64 doubles
 template <typename T>
 int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,

@@ -156,66 +156,59 @@ __global__ void k_put_tile(const double* __restrict__ D, long long sD, double* _
   for (int e = t; e < TM * TM; e += 256) x[(long long)(e / TM) * ld + (e % TM)] = d[e];
 }
 
-// x_p = Ainv_p b_p, one wavefront per row, double2 loads, deterministic wave reduction.
-__global__ __launch_bounds__(256) void k_gemv(int np, const double* __restrict__ Ainv, const double* __restrict__ b,
-                                              double* __restrict__ x) {
-  const int p = blockIdx.y;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= np) return;
-  const double* a = Ainv + (long long)p * np * np + (long long)row * np;
-  const double* bp = b + (long long)p * np;
-  double acc = 0.0;
-  for (int j = 2 * lane; j < np; j += 128) {
-    const double2 av = *reinterpret_cast<const double2*>(a + j);
-    const double2 bv = *reinterpret_cast<const double2*>(bp + j);
-    acc += av.x * bv.x + av.y * bv.y;
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) x[(long long)p * np + row] = acc;
+// Tile q = J (J + 1) / 2 + I of the packed lower triangle holds block (J, I), J >= I.
+__device__ __forceinline__ void tile_of(int q, int& J, int& I) {
+  J = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= q) ++J;
+  while (J * (J + 1) / 2 > q) --J;
+  I = q - J * (J + 1) / 2;
+}
+
+// Copy the lower 64x64 blocks of each np x np matrix into contiguous 32 KB tiles.
+__global__ __launch_bounds__(256) void k_pack_tiles(int64_t np, int ntiles, const double* __restrict__ dense,
+                                                    double* __restrict__ packed) {
+  const int q = blockIdx.x, p = blockIdx.y;
+  int J, I;
+  tile_of(q, J, I);
+  const double* src = dense + (int64_t)p * np * np + (int64_t)J * TM * np + (int64_t)I * TM;
+  double* dst = packed + ((int64_t)p * ntiles + q) * TM * TM;
+  for (int e = threadIdx.x; e < TM * TM; e += 256) dst[e] = src[(int64_t)(e / TM) * np + e % TM];
 }
 
 // x = A^{-1} b for the symmetric dense inverse, reading only its lower 64x64
-// blocks, each exactly once.  Block (J, I), J >= I, of problem p is handled
-// by one wavefront: it contributes A_JI b_I to rows of block J and, when
-// J > I, A_JI^T b_J to rows of block I.  The 64-vectors land in
-// part[p][row block][column block]; a second kernel sums them in a fixed order.
-// b and x are level vectors (nl rows per problem); padding rows read as 0.
+// blocks, each exactly once, from the packed contiguous tiles.  Tile (J, I) of
+// problem p is handled by one wavefront that streams its 64 rows (one 512 B
+// load each): it contributes A_JI b_I to rows of block J (row sums, through an
+// LDS transpose) and, when J > I, A_JI^T b_J to rows of block I (column sums,
+// in registers).  The 64-vectors land in part[p][row block][column block]; a
+// second kernel sums them in a fixed order.  b and x are level vectors (nl rows
+// per problem); padding rows read as 0.
 template <typename T>
-__global__ __launch_bounds__(256) void k_symv_blocks(int nb, int64_t nl, int64_t np, const double* __restrict__ Ainv,
-                                                     const T* __restrict__ b, double* __restrict__ part) {
-  __shared__ double tile[TM][TM + 1];
-  __shared__ double bi[TM], bj[TM];
-  const int p = blockIdx.y;
-  // map the linear block index to (J, I) with J >= I: q = J (J + 1) / 2 + I
-  const int q = blockIdx.x;
-  int J = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-  while ((J + 1) * (J + 2) / 2 <= q) ++J;
-  while (J * (J + 1) / 2 > q) --J;
-  const int I = q - J * (J + 1) / 2;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const double* A = Ainv + (int64_t)p * np * np;
+__global__ __launch_bounds__(TM) void k_symv_tiles(int nb, int ntiles, int64_t nl, const double* __restrict__ packed,
+                                                   const T* __restrict__ b, double* __restrict__ part) {
+  __shared__ double prod[TM][TM + 1];
+  const int q = blockIdx.x, p = blockIdx.y, lane = threadIdx.x;
+  int J, I;
+  tile_of(q, J, I);
   const T* bp = b + (int64_t)p * nl;
-  if (w == 0) {
-    const int64_t ri = (int64_t)I * TM + lane;
-    bi[lane] = ri < nl ? (double)bp[ri] : 0.0;
-  } else if (w == 1) {
-    const int64_t rj = (int64_t)J * TM + lane;
-    bj[lane] = rj < nl ? (double)bp[rj] : 0.0;
+  const int64_t ri = (int64_t)I * TM + lane, rj = (int64_t)J * TM + lane;
+  const double bI = ri < nl ? (double)bp[ri] : 0.0;
+  const double bJ = rj < nl ? (double)bp[rj] : 0.0;
+  const double* src = packed + ((int64_t)p * ntiles + q) * TM * TM + lane;
+  double col = 0.0;
+#pragma unroll 16
+  for (int a = 0; a < TM; ++a) {
+    const double v = src[a * TM];
+    col += v * __shfl(bJ, a, TM);
+    prod[a][lane] = v * bI;
   }
-  // each wave loads 16 rows of the tile, one 512 B row segment per load
-  for (int a = w; a < TM; a += 4) tile[a][lane] = A[((int64_t)J * TM + a) * np + (int64_t)I * TM + lane];
   __syncthreads();
+  double row = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < TM; ++c) row += prod[lane][c];
   double* out = part + (int64_t)p * nb * nb * TM;
-  if (w == 0) {
-    double row = 0.0;  // (A_JI b_I)_lane
-    for (int c = 0; c < TM; ++c) row += tile[lane][c] * bi[c];
-    out[((int64_t)J * nb + I) * TM + lane] = row;
-  } else if (w == 1 && J > I) {
-    double col = 0.0;  // (A_JI^T b_J)_lane
-    for (int a = 0; a < TM; ++a) col += tile[a][lane] * bj[a];
-    out[((int64_t)I * nb + J) * TM + lane] = col;
-  }
+  out[((int64_t)J * nb + I) * TM + lane] = row;
+  if (J > I) out[((int64_t)I * nb + J) * TM + lane] = col;
 }
 
 // x_I = sum_J part[I][J]: four waves each sum a quarter of the J range, combined in a fixed order.
@@ -309,8 +302,8 @@ int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np64, double* dense, in
 template <typename T>
 int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,
                        double* part) {
-  const int nb = (int)(np / TM);
-  hipLaunchKernelGGL(k_symv_blocks<T>, dim3(nb * (nb + 1) / 2, nbatch), dim3(256), 0, s, nb, nl, np, ainv, b, part);
+  const int nb = (int)(np / TM), ntiles = nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(ntiles, nbatch), dim3(TM), 0, s, nb, ntiles, nl, ainv, b, part);
   hipLaunchKernelGGL(k_symv_sum<T>, dim3(nb, nbatch), dim3(256), 0, s, nb, nl, (const double*)part, x);
   return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
 }
@@ -319,9 +312,11 @@ template int launch_coarse_symv<double>(hipStream_t, int, int64_t, int64_t, cons
 template int launch_coarse_symv<float>(hipStream_t, int, int64_t, int64_t, const double*, const float*, float*,
                                        double*);
 
-int launch_coarse_gemv(hipStream_t s, int nbatch, int64_t np, const double* ainv, const double* b, double* x) {
-  dim3 grid((unsigned)((np + 3) / 4), nbatch);
-  hipLaunchKernelGGL(k_gemv, grid, dim3(256), 0, s, (int)np, ainv, b, x);
+int pack_lower_tiles(hipStream_t s, int nbatch, int64_t np, const double* dense, double** packed) {
+  const int nb = (int)(np / TM), ntiles = nb * (nb + 1) / 2;
+  *packed = nullptr;
+  if (hipMalloc(packed, sizeof(double) * (size_t)nbatch * ntiles * TM * TM) != hipSuccess) return AMG_ENOMEM;
+  hipLaunchKernelGGL(k_pack_tiles, dim3(ntiles, nbatch), dim3(256), 0, s, np, ntiles, dense, *packed);
   return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
 }
 

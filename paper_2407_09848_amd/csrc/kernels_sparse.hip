@@ -333,25 +333,6 @@ __global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restric
   y[i] = (Tout)x[i];
 }
 
-// level vector (nbatch blocks of nl) <-> padded dense layout (nbatch blocks of np >= nl, pad = 0)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pad_in(int64_t total, int64_t nl, int64_t np, const T* __restrict__ b,
-                                                   double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const int64_t p = i / np, j = i % np;
-  out[i] = j < nl ? (double)b[p * nl + j] : 0.0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pad_out(int64_t total, int64_t nl, int64_t np,
-                                                    const double* __restrict__ in, T* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= total) return;
-  const int64_t p = i / nl, j = i % nl;
-  x[i] = (T)in[p * np + j];
-}
-
 // ---------------------------------------------------------------------------
 // CG kernels (float64): fused SpMV + dot, update + dot, and a single-block
 // second-stage reduction that also forms the CG scalars on the device.
@@ -740,20 +721,6 @@ int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y) {
   return LAUNCH_OK();
 }
 
-template <typename T>
-int launch_pad_in(hipStream_t s, int nbatch, int64_t nl, int64_t np, const T* b, double* out) {
-  const int64_t total = (int64_t)nbatch * np;
-  hipLaunchKernelGGL(k_pad_in<T>, dim3(grid_for(total)), dim3(kBlock), 0, s, total, nl, np, b, out);
-  return LAUNCH_OK();
-}
-
-template <typename T>
-int launch_pad_out(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* in, T* x) {
-  const int64_t total = (int64_t)nbatch * nl;
-  hipLaunchKernelGGL(k_pad_out<T>, dim3(grid_for(total)), dim3(kBlock), 0, s, total, nl, np, in, x);
-  return LAUNCH_OK();
-}
-
 int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
                 double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(n);
@@ -843,9 +810,8 @@ int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
   template int launch_spmv_add<T>(hipStream_t, const Ell<T>&, const T*, T*);                                 \
   template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*, Wt);                                \
   template int launch_copy<T>(hipStream_t, int64_t, const T*, T*);                                           \
-  template int launch_fill<T>(hipStream_t, int64_t, T, T*);                                                   \
-  template int launch_pad_in<T>(hipStream_t, int, int64_t, int64_t, const T*, double*);                       \
-  template int launch_pad_out<T>(hipStream_t, int, int64_t, int64_t, const double*, T*);
+  template int launch_fill<T>(hipStream_t, int64_t, T, T*);
+
 
 INST(double)
 INST(float)

@@ -85,8 +85,6 @@ void release(Handle* h) {
     free_ell(L.PT32);
   }
   hipFree(h->ainv);
-  hipFree(h->cb);
-  hipFree(h->cx);
   hipFree(h->cpart);
   hipFree(h->partial);
   hipFree(h->scal);
@@ -641,12 +639,15 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     Level& L = h->lv.back();
     h->ncl = L.n / h->nbatch;
     h->ncp = (h->ncl + kDenseTile - 1) / kDenseTile * kDenseTile;
-    AMGP_TRY(dalloc(&h->ainv, (int64_t)h->nbatch * h->ncp * h->ncp));
-    AMGP_TRY(dalloc(&h->cb, (int64_t)h->nbatch * h->ncp));
-    AMGP_TRY(dalloc(&h->cx, (int64_t)h->nbatch * h->ncp));
     AMGP_TRY(dalloc(&h->cpart, (int64_t)h->nbatch * (h->ncp / kDenseTile) * (h->ncp / kDenseTile) * kDenseTile));
-    AMGP_TRY(launch_to_dense(s, h->nbatch, h->ncl, h->ncp, L.csr_ptr, L.csr_col, L.csr_val, h->ainv, h->dflag));
-    AMGP_TRY(dense_spd_inverse(s, h->nbatch, h->ncp, h->ainv, h->dflag));
+    double* dense = nullptr;
+    AMGP_TRY(dalloc(&dense, (int64_t)h->nbatch * h->ncp * h->ncp));
+    int rc = launch_to_dense(s, h->nbatch, h->ncl, h->ncp, L.csr_ptr, L.csr_col, L.csr_val, dense, h->dflag);
+    if (rc == AMG_OK) rc = dense_spd_inverse(s, h->nbatch, h->ncp, dense, h->dflag);
+    if (rc == AMG_OK) rc = pack_lower_tiles(s, h->nbatch, h->ncp, dense, &h->ainv);
+    if (rc == AMG_OK && hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
+    hipFree(dense);
+    if (rc != AMG_OK) return rc;
     int fl[F_NFLAG];
     AMGP_TRY(read_flags(h, s, fl));
     if (fl[F_NOTSPD]) return AMG_ENOTSPD;
