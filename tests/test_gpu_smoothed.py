@@ -175,3 +175,20 @@ def test_option_validation(amg):
             with hierarchy(A, max_coarse=64, **bad):
                 pass
         assert e.value.code == amg.AMG_EINVAL
+
+
+def test_product_capacity_error(amg):
+    """A Galerkin product row with more distinct columns than the LDS table holds is reported as
+    AMG_ECAPACITY, not computed wrongly: the dense 8000 x 8000 SPD matrix, aggregated in pairs and
+    smoothed, gives rows of A P_hat with 4000 distinct columns."""
+    torch_cuda()
+    n = 8000
+    rng = np.random.default_rng(2)
+    Bm = rng.uniform(-1, 1, (n, 8))
+    dense = Bm @ Bm.T / 8.0 + n * np.eye(n)
+    A = W.CSR(n=n, row_ptr=(np.arange(n + 1) * n).astype(np.int32), col=np.tile(np.arange(n, dtype=np.int32), n),
+              val=dense.ravel(), grid=(n, 1, 1))
+    with pytest.raises(amg.AmgError) as e:
+        with hierarchy(A, max_coarse=100, smoothed=True):
+            pass
+    assert e.value.code == amg.AMG_ECAPACITY
