@@ -67,6 +67,10 @@ extern "C" {
                         accumulation; the coarsest solve, the outer CG residual, its dot
                         products and direction updates stay float64 */
 
+/* ---- aggregation ---- */
+#define AMG_AGG_BOX       0  /* fixed boxes of the structured grid (agg_edge) */
+#define AMG_AGG_MATCHING  1  /* compatible weighted matching (Section 4), one problem only */
+
 /* Highest supported polynomial degree (tabulated constants exist for 1..AMG_MAX_DEGREE). */
 #define AMG_MAX_DEGREE 12
 
@@ -84,6 +88,14 @@ typedef struct amg_opts {
                             omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem (Section 4) */
   int32_t coarse_sweeps; /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps from
                             zero (at most 1000) instead of the dense Cholesky factorisation */
+  int32_t aggregation;   /* AMG_AGG_BOX (0) or AMG_AGG_MATCHING: aggregates from match_steps
+                            approximate maximum-weight matchings of the graph of A_l, edge weight
+                            1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2) for the smooth vector w
+                            (ones on level 0, then the coarse one), matched greedily in decreasing
+                            weight; a pair forms an aggregate, the tentative prolongator column
+                            holds w restricted to it, normalised.  Requires nbatch = 1 and a
+                            structurally symmetric A; the grid extents are not used then */
+  int32_t match_steps;   /* matching steps per level, 1..3 (aggregates of up to 2^steps rows); 0 means 3 */
 } amg_opts;
 
 /* ---------------------------------------------------------------------------

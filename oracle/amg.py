@@ -117,15 +117,23 @@ def smoothed_prolongator(A, Phat, nbatch=1):
     return (Phat - S @ (A @ Phat)).tocsr()
 
 
-def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=False, coarse_sweeps=0):
+def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=False, coarse_sweeps=0,
+                    aggregation="box", match_steps=3):
     """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse.
 
     ``agg_edge``: edge of the box aggregates; ``smoothed``: use the smoothed
     prolongator; ``coarse_sweeps`` > 0: solve the coarsest level by that many
     l1-Jacobi sweeps from zero instead of the dense Cholesky factorisation.
     Outside the default (2x2x2 boxes, plain P) the smoothed P and the Galerkin
-    operators pass through drop_small.
+    operators pass through drop_small.  ``aggregation="matching"``: aggregates
+    from ``match_steps`` compatible weighted matchings (oracle.matching) instead
+    of boxes (one problem only).
     """
+    from .matching import matching_prolongator
+    if aggregation not in ("box", "matching"):
+        raise ValueError(aggregation)
+    if aggregation == "matching" and nbatch != 1:
+        raise ValueError("matching aggregation takes one problem")
     A = sp.csr_matrix(A)
     A.sort_indices()
     H = Hierarchy(coarse_sweeps=int(coarse_sweeps))
@@ -133,13 +141,19 @@ def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=Fal
     if nbatch > 1:
         g = (g[0], g[1], g[2] // nbatch)
     H.levels.append(Level(A=A, Minv=l1_diagonal(A), grid=g, nbatch=nbatch))
+    wsmooth = np.ones(A.shape[0])
     while A.shape[0] // nbatch > max_coarse:
-        agg, gc = box_aggregates(g, nbatch, agg_edge)
-        nc = int(np.prod(gc)) * nbatch
+        if aggregation == "matching":
+            Pm, wsmooth = matching_prolongator(A, wsmooth, match_steps)
+            nc = Pm.shape[1]
+            gc = (nc, 1, 1)
+        else:
+            agg, gc = box_aggregates(g, nbatch, agg_edge)
+            nc = int(np.prod(gc)) * nbatch
+            Pm = prolongator(agg, nc)
         if nc >= A.shape[0]:
             raise ValueError("aggregation does not reduce the level")
-        Pm = prolongator(agg, nc)
-        general = smoothed or agg_edge != 2
+        general = smoothed or agg_edge != 2 or aggregation == "matching"
         if smoothed:
             Pm = drop_small(smoothed_prolongator(A, Pm, nbatch))
         Pm.sort_indices()

@@ -76,6 +76,7 @@ struct Level {
   int64_t nc = 0;                 // rows of level + 1
   int32_t* agg = nullptr;         // [n] aggregate of each row
   int32_t* children = nullptr;    // [nc * 8] rows of each aggregate, ascending, -1 padded (2x2x2 boxes)
+  double* wsmooth = nullptr;      // smooth vector of the matching aggregation (device, n), null: ones
   // explicit prolongator (smoothed, or boxes of another edge): P (n x nc) and P^T (nc x n)
   bool general = false;
   Ell<double> P64, PT64;
@@ -136,6 +137,8 @@ struct Handle {
   int agg_edge = 2;       // box aggregate edge
   bool smoothed = false;  // smoothed prolongator
   int coarse_sweeps = 0;  // > 0: l1-Jacobi sweeps instead of the dense coarsest solve
+  int aggregation = AMG_AGG_BOX;
+  int match_steps = 3;    // matching steps per level (aggregates of up to 2^steps rows)
   std::vector<Level> lv;
   // coarsest level: dense inverse per problem, padded to ncp
   int64_t ncl = 0;   // rows per problem on the coarsest level
@@ -289,8 +292,15 @@ int spgemm(hipStream_t s, const Csr& X, const Csr& Y, Csr* C, int* flag);  // C 
 int drop_small(hipStream_t s, Csr* a, double tau);
 int transpose(hipStream_t s, const Csr& a, Csr* t);
 int tentative_prolongator(hipStream_t s, int64_t n, int64_t nc, const int32_t* agg, Csr* P);
-// P = (I - omega D^{-1} A) P_hat, omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem
-int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const int32_t* agg, int64_t nc, Csr* P,
+// P = (I - omega D^{-1} A) P_hat for a P_hat with one entry per row,
+// omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem
+int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const Csr& Phat, Csr* P, int* flag);
+// host exclusive scan of cnt[0, m) into ptr[0, m]; returns the total (rc = AMG_ECAPACITY beyond int32)
+int64_t scan_ptr(hipStream_t s, int64_t m, const int32_t* cnt, int32_t* ptr, int* rc);
+// ---- compatible weighted matching (kernels_match.hip) ----
+// composite tentative prolongator of `steps` matching steps on A (structurally symmetric, ascending
+// columns) from the smooth vector w0 (null: ones); *wnext (device, ncols entries) is the coarse one
+int matching_prolongator(hipStream_t s, const Csr& A, const double* w0, int steps, Csr* Phat, double** wnext,
                          int* flag);
 int galerkin_general(hipStream_t s, const Csr& A, const Csr& P, const Csr& PT, Csr* Ac, int* flag);
 void free_ell(Ell<float>& e);

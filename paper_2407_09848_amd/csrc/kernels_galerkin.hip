@@ -247,15 +247,18 @@ __global__ void k_diag_ratio(int64_t n, int64_t rpp, const int32_t* __restrict__
   atomicMax(&lam[i / rpp], (unsigned long long)__double_as_longlong(s / d));
 }
 
-// P = P_hat - omega_p D^{-1} (A P_hat), in place on the pattern of A P_hat (which holds agg(i)).
+// P = P_hat - omega_p D^{-1} (A P_hat), in place on the pattern of A P_hat, which holds the
+// single entry (hcol[i], hval[i]) of row i of P_hat.
 __global__ void k_smooth_prol(int64_t n, int64_t rpp, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                              double* __restrict__ val, const int32_t* __restrict__ agg,
-                              const double* __restrict__ diag, const double* __restrict__ omega) {
+                              double* __restrict__ val, const int32_t* __restrict__ hcol,
+                              const double* __restrict__ hval, const double* __restrict__ diag,
+                              const double* __restrict__ omega) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double s = omega[i / rpp] / diag[i];
-  const int a = agg[i];
-  for (int p = ptr[i]; p < ptr[i + 1]; ++p) val[p] = (col[p] == a ? 1.0 : 0.0) - s * val[p];
+  const int a = hcol[i];
+  const double h = hval[i];
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) val[p] = (col[p] == a ? h : 0.0) - s * val[p];
 }
 
 __global__ void k_identity_rows(int64_t n, const int32_t* __restrict__ agg, int32_t* __restrict__ ptr,
@@ -267,37 +270,6 @@ __global__ void k_identity_rows(int64_t n, const int32_t* __restrict__ agg, int3
     col[i] = agg[i];
     val[i] = 1.0;
   }
-}
-
-// Host exclusive scan of cnt[0, m) into ptr[0, m]; returns the total or -1 beyond int32.
-int64_t scan_to_ptr(hipStream_t s, int64_t m, const int32_t* cnt, int32_t* ptr, int* rc) {
-  std::vector<int32_t> h(m);
-  *rc = AMG_OK;
-  if (m > 0 && hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s) != hipSuccess) {
-    *rc = AMG_EHIP;
-    return -1;
-  }
-  if (hipStreamSynchronize(s) != hipSuccess) {
-    *rc = AMG_EHIP;
-    return -1;
-  }
-  std::vector<int32_t> p(m + 1);
-  int64_t acc = 0;
-  for (int64_t i = 0; i < m; ++i) {
-    p[i] = (int32_t)acc;
-    acc += h[i];
-    if (acc >= (int64_t)INT32_MAX) {
-      *rc = AMG_ECAPACITY;
-      return -1;
-    }
-  }
-  p[m] = (int32_t)acc;
-  if (hipMemcpyAsync(ptr, p.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
-    *rc = AMG_EHIP;
-    return -1;
-  }
-  return acc;
 }
 
 template <int CAP>
@@ -333,6 +305,37 @@ int read_flag(hipStream_t s, const int* flag, int which) {
 }
 
 }  // namespace
+
+// Host exclusive scan of cnt[0, m) into ptr[0, m]; returns the total or -1 beyond int32.
+int64_t scan_ptr(hipStream_t s, int64_t m, const int32_t* cnt, int32_t* ptr, int* rc) {
+  std::vector<int32_t> h(m);
+  *rc = AMG_OK;
+  if (m > 0 && hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s) != hipSuccess) {
+    *rc = AMG_EHIP;
+    return -1;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    *rc = AMG_EHIP;
+    return -1;
+  }
+  std::vector<int32_t> p(m + 1);
+  int64_t acc = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    p[i] = (int32_t)acc;
+    acc += h[i];
+    if (acc >= (int64_t)INT32_MAX) {
+      *rc = AMG_ECAPACITY;
+      return -1;
+    }
+  }
+  p[m] = (int32_t)acc;
+  if (hipMemcpyAsync(ptr, p.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    *rc = AMG_EHIP;
+    return -1;
+  }
+  return acc;
+}
 
 void free_csr(Csr& a) {
   hipFree(a.ptr);
@@ -376,7 +379,7 @@ int spgemm(hipStream_t s, const Csr& X, const Csr& Y, Csr* C, int* flag) {
     hipFree(cnt);
     return AMG_ENOMEM;
   }
-  const int64_t nnz = scan_to_ptr(s, m, cnt, c.ptr, &rc);
+  const int64_t nnz = scan_ptr(s, m, cnt, c.ptr, &rc);
   hipFree(cnt);
   if (rc != AMG_OK) {
     free_csr(c);
@@ -410,7 +413,7 @@ int drop_small(hipStream_t s, Csr* a, double tau) {
     return AMG_ENOMEM;
   }
   int rc = AMG_OK;
-  o.nnz = scan_to_ptr(s, a->m, kept, o.ptr, &rc);
+  o.nnz = scan_ptr(s, a->m, kept, o.ptr, &rc);
   hipFree(kept);
   if (rc != AMG_OK) {
     free_csr(o);
@@ -445,7 +448,7 @@ int transpose(hipStream_t s, const Csr& a, Csr* t) {
     hipLaunchKernelGGL(k_col_count, dim3(grid_for(a.nnz)), dim3(kBlock), 0, s, a.nnz, a.col, cnt);
     if (hipMalloc(&o.ptr, sizeof(int32_t) * (o.m + 1)) != hipSuccess) rc = AMG_ENOMEM;
   }
-  if (rc == AMG_OK) scan_to_ptr(s, o.m, cnt, o.ptr, &rc);
+  if (rc == AMG_OK) scan_ptr(s, o.m, cnt, o.ptr, &rc);
   if (rc == AMG_OK && (hipMalloc(&o.col, sizeof(int32_t) * std::max<int64_t>(o.nnz, 1)) != hipSuccess ||
                        hipMalloc(&o.val, sizeof(double) * std::max<int64_t>(o.nnz, 1)) != hipSuccess))
     rc = AMG_ENOMEM;
@@ -484,14 +487,10 @@ int tentative_prolongator(hipStream_t s, int64_t n, int64_t nc, const int32_t* a
   return AMG_OK;
 }
 
-int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const int32_t* agg, int64_t nc, Csr* P,
-                         int* flag) {
+int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const Csr& Ph, Csr* P, int* flag) {
   const int64_t n = A.m, rpp = n / nbatch;
-  Csr Ph;
-  AMGP_TRY(tentative_prolongator(s, n, nc, agg, &Ph));
   Csr AP;
   int rc = spgemm(s, A, Ph, &AP, flag);
-  free_csr(Ph);
   if (rc != AMG_OK) return rc;
   double* diag = nullptr;
   unsigned long long* lam = nullptr;
@@ -514,8 +513,8 @@ int smoothed_prolongator(hipStream_t s, const Csr& A, int nbatch, const int32_t*
     if (hipMemcpyAsync(om, ho.data(), sizeof(double) * nbatch, hipMemcpyHostToDevice, s) != hipSuccess) rc = AMG_EHIP;
   }
   if (rc == AMG_OK) {
-    hipLaunchKernelGGL(k_smooth_prol, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rpp, AP.ptr, AP.col, AP.val, agg,
-                       diag, om);
+    hipLaunchKernelGGL(k_smooth_prol, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rpp, AP.ptr, AP.col, AP.val, Ph.col,
+                       Ph.val, diag, om);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
   }
   hipFree(diag);

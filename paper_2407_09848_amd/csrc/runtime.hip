@@ -79,6 +79,7 @@ void release(Handle* h) {
     free_vecs(L.v32, true);
     hipFree(L.agg);
     hipFree(L.children);
+    hipFree(L.wsmooth);
     free_ell(L.P64);
     free_ell(L.PT64);
     free_ell(L.P32);
@@ -544,7 +545,7 @@ struct CsrHold {
   ~CsrHold() { free_csr(c); }
 };
 
-int general_level(Handle* h, hipStream_t s, Level& L, Level* C) {
+Csr level_csr(const Level& L) {
   Csr A;
   A.m = L.n;
   A.ncols = L.n;
@@ -552,11 +553,25 @@ int general_level(Handle* h, hipStream_t s, Level& L, Level* C) {
   A.ptr = L.csr_ptr;
   A.col = L.csr_col;
   A.val = L.csr_val;
-  CsrHold P, PT, Ac;
-  if (h->smoothed)
-    AMGP_TRY(smoothed_prolongator(s, A, h->nbatch, L.agg, L.nc, &P.c, h->dflag));
-  else
-    AMGP_TRY(tentative_prolongator(s, L.n, L.nc, L.agg, &P.c));
+  return A;
+}
+
+// Phat: the tentative prolongator (taken over); box aggregates when null (from L.agg)
+int general_level(Handle* h, hipStream_t s, Level& L, Level* C, Csr* Phat) {
+  const Csr A = level_csr(L);
+  CsrHold Ph, P, PT, Ac;
+  if (Phat) {
+    Ph.c = *Phat;
+    *Phat = Csr();
+  } else {
+    AMGP_TRY(tentative_prolongator(s, L.n, L.nc, L.agg, &Ph.c));
+  }
+  if (h->smoothed) {
+    AMGP_TRY(smoothed_prolongator(s, A, h->nbatch, Ph.c, &P.c, h->dflag));
+  } else {
+    P.c = Ph.c;
+    Ph.c = Csr();
+  }
   AMGP_TRY(transpose(s, P.c, &PT.c));
   AMGP_TRY(galerkin_general(s, A, P.c, PT.c, &Ac.c, h->dflag));
   AMGP_TRY(build_ell64(s, P.c.m, P.c.ptr, P.c.col, P.c.val, &L.P64, P.c.ncols));
@@ -577,6 +592,8 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   h->agg_edge = o->agg_edge > 0 ? o->agg_edge : 2;
   h->smoothed = o->smoothed != 0;
   h->coarse_sweeps = o->coarse_sweeps;
+  h->aggregation = o->aggregation;
+  h->match_steps = o->match_steps > 0 ? o->match_steps : 3;
   {
     const char* e = std::getenv("AMGP_NO_GRAPH");
     h->use_graphs = !(e && e[0] == '1');
@@ -610,6 +627,27 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     AMGP_TRY(build_ell64(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, &L.A64));
     const int64_t per = L.n / h->nbatch;
     if (per <= h->max_coarse) break;
+    if (h->aggregation == AMG_AGG_MATCHING) {
+      // compatible weighted matching: aggregates of up to 2^match_steps rows (Section 4)
+      CsrHold Ph;
+      double* wnext = nullptr;
+      AMGP_TRY(matching_prolongator(s, level_csr(L), L.wsmooth, h->match_steps, &Ph.c, &wnext, h->dflag));
+      const int64_t nc = Ph.c.ncols;
+      if (nc >= L.n) {
+        hipFree(wnext);
+        break;
+      }
+      L.nc = nc;
+      L.general = true;
+      Level C;
+      C.n = nc;
+      C.nx = (int)nc;
+      C.wsmooth = wnext;
+      const int rc = general_level(h, s, L, &C, &Ph.c);
+      h->lv.push_back(C);  // owned by the handle from here on, also on error
+      if (rc != AMG_OK) return rc;
+      continue;
+    }
     int cx, cy, cz;
     const int e = h->agg_edge;
     auto cdim = [e](int v) { return v == 1 ? 1 : (v + e - 1) / e; };
@@ -629,7 +667,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
       AMGP_TRY(galerkin(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, L.agg, nc, L.children, &C.csr_ptr, &C.csr_col,
                         &C.csr_val, &C.nnz, h->dflag));
     } else {
-      AMGP_TRY(general_level(h, s, L, &C));
+      AMGP_TRY(general_level(h, s, L, &C, nullptr));
     }
     h->lv.push_back(C);
   }
@@ -822,6 +860,9 @@ int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d
   if (o.agg_edge < 0 || o.agg_edge == 1 || o.agg_edge > 4) return AMG_EINVAL;
   if (o.smoothed != 0 && o.smoothed != 1) return AMG_EINVAL;
   if (o.coarse_sweeps < 0 || o.coarse_sweeps > 1000) return AMG_EINVAL;
+  if (o.aggregation != AMG_AGG_BOX && o.aggregation != AMG_AGG_MATCHING) return AMG_EINVAL;
+  if (o.aggregation == AMG_AGG_MATCHING && nb != 1) return AMG_EINVAL;
+  if (o.match_steps < 0 || o.match_steps > 3) return AMG_EINVAL;
   amg_handle* h = new (std::nothrow) amg_handle;
   if (!h) return AMG_ENOMEM;
   const int rc = amgp::setup(&h->impl, n, nnz, d_row_ptr, d_col, d_val, &o, (hipStream_t)stream);
