@@ -324,18 +324,21 @@ def main():
         amg.amg_destroy(h32)
         # the paper's own preconditioner ingredients (Section 4): smoothed prolongator,
         # 30 l1-Jacobi sweeps on the coarsest level, flexible CG
-        t0 = time.perf_counter()
-        try:
-            hsa = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64, 2, True, 30)
-        except amg.AmgError as e:
-            hsa = None
-            variants["smoothed_p_sweeps30_fcg"] = {"error": str(e)}
-        if hsa is not None:
+        # (on the box aggregates and on compatible-matching aggregates of up to 8 rows)
+        for tag, agg in (("box", amg.AMG_AGG_BOX), ("matching", amg.AMG_AGG_MATCHING)):
+            t0 = time.perf_counter()
+            try:
+                hsa = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64, 2, True, 30, agg)
+            except amg.AmgError as e:
+                hsa = None
+                variants[f"{tag}_smoothed_p_sweeps30_fcg"] = {"error": str(e)}
+            if hsa is None:
+                continue
             torch.cuda.synchronize()
             sa_setup = time.perf_counter() - t0
             for kind in (args.kind, 3):
                 tm, itv = time_solve(hsa, kind, args.degree, flexible=True)
-                variants[f"fp64_{names[kind]}_k{args.degree}_smoothed_p_sweeps30_fcg"] = {
+                variants[f"fp64_{names[kind]}_k{args.degree}_{tag}_smoothed_p_sweeps30_fcg"] = {
                     "ms": round(tm, 3), "iters": itv, "setup_s": round(sa_setup, 3),
                     "levels": [amg.amg_level_info(hsa, l) for l in range(amg.amg_num_levels(hsa))]}
             amg.amg_destroy(hsa)

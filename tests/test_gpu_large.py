@@ -165,7 +165,10 @@ def test_aniso_full_size():
     As = A.to_scipy()
     bd = dev(b)
     nb = np.linalg.norm(b)
-    for name, opts, flex in (("box", {}, False), ("smoothed+sweeps", dict(smoothed=True, coarse_sweeps=30), True)):
+    import paper_2407_09848_amd as amg_
+    for name, opts, flex in (("box", {}, False), ("smoothed+sweeps", dict(smoothed=True, coarse_sweeps=30), True),
+                             ("matching+smoothed+sweeps", dict(aggregation=amg_.AMG_AGG_MATCHING, smoothed=True,
+                                                               coarse_sweeps=30), True)):
         t = time.time()
         with hierarchy(A, **opts) as h:
             sizes = [amg.amg_level_info(h, l) for l in range(amg.amg_num_levels(h))]
@@ -180,3 +183,28 @@ def test_aniso_full_size():
                 tr = np.linalg.norm(b - As @ host(x)) / nb
                 _log(f"aniso {name} kind {kind} k 2: rc {rc} iters {it} relres {rel:.2e} true {tr:.2e} {dt:.3f} s")
                 assert rc == amg.AMG_OK and tr <= 2e-8
+
+
+def test_c2_matching_paper_configuration():
+    """The paper's Poisson configuration at 128^3: compatible matching (aggregates of up to 8),
+    smoothed prolongator, 30 coarse l1-Jacobi sweeps, flexible CG; every kind at k = 1..6."""
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    A, b, _ = W.config_problem(2)
+    As = A.to_scipy()
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    t = time.time()
+    with hierarchy(A, aggregation=amg.AMG_AGG_MATCHING, smoothed=True, coarse_sweeps=30) as h:
+        sizes = [amg.amg_level_info(h, l) for l in range(amg.amg_num_levels(h))]
+        _log(f"C2 matching: setup {time.time() - t:.2f} s, levels {sizes}")
+        for kind in (0, 1, 2, 3):
+            its = []
+            for k in range(1, 7):
+                x = nan_vec(A.n)
+                rc, it, rel, _ = amg.pcg_solve(h, kind, k, bd, x, True, 1e-8, 1000, True)
+                torch.cuda.synchronize()
+                tr = np.linalg.norm(b - As @ host(x)) / nb
+                assert rc == amg.AMG_OK and tr <= 2e-8, (kind, k, rc, tr)
+                its.append(it)
+            _log(f"C2 matching kind {kind}: iterations for k = 1..6: {its}")

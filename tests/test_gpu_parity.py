@@ -293,6 +293,24 @@ def test_pcg_iterations_match_oracle_32(amg, kind):
             assert relerr(host(x), ro.x) <= 1e-10
 
 
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_pcg_high_degrees_match_oracle(amg, kind):
+    """Degrees 8..12 (the higher-degree trends of the supplement): exact PCG counts at 24^3."""
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=24)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid, max_coarse=512)
+    with hierarchy(A, max_coarse=512) as h:
+        for k in range(8, 13):
+            x = nan_vec(A.n)
+            rc, it, rel, hist = amg.pcg_solve(h, kind, k, dev(b), x, True, 1e-8, 1000, False, True)
+            torch.cuda.synchronize()
+            beta, _ = oracle_params(kind, k)
+            ro, _ = OA.amg_pcg(As, b, A.grid, kind, k, H=H, beta=beta)
+            assert rc == amg.AMG_OK and it == ro.iters, (kind, k, it, ro.iters)
+            assert np.allclose(hist, ro.history, rtol=1e-6, atol=0)
+
+
 def _golden_c2():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_pcg_iterations_128.txt")
     rows = []
