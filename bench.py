@@ -324,21 +324,24 @@ def main():
         amg.amg_destroy(h32)
         # the paper's own preconditioner ingredients (Section 4): smoothed prolongator,
         # 30 l1-Jacobi sweeps on the coarsest level, flexible CG
-        # (on the box aggregates and on compatible-matching aggregates of up to 8 rows)
-        for tag, agg in (("box", amg.AMG_AGG_BOX), ("matching", amg.AMG_AGG_MATCHING)):
+        # (on the box aggregates and on compatible-matching aggregates of up to 8 rows), and the
+        # smoothed prolongator with the dense Cholesky coarsest solve of the plain configuration
+        for tag, agg, sweeps in (("box", amg.AMG_AGG_BOX, 30), ("matching", amg.AMG_AGG_MATCHING, 30),
+                                 ("box", amg.AMG_AGG_BOX, 0)):
+            name = f"{tag}_smoothed_p_" + (f"sweeps{sweeps}_fcg" if sweeps else "cholesky_fcg")
             t0 = time.perf_counter()
             try:
-                hsa = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64, 2, True, 30, agg)
+                hsa = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64, 2, True, sweeps, agg)
             except amg.AmgError as e:
                 hsa = None
-                variants[f"{tag}_smoothed_p_sweeps30_fcg"] = {"error": str(e)}
+                variants[name] = {"error": str(e)}
             if hsa is None:
                 continue
             torch.cuda.synchronize()
             sa_setup = time.perf_counter() - t0
             for kind in (args.kind, 3):
                 tm, itv = time_solve(hsa, kind, args.degree, flexible=True)
-                variants[f"fp64_{names[kind]}_k{args.degree}_{tag}_smoothed_p_sweeps30_fcg"] = {
+                variants[f"fp64_{names[kind]}_k{args.degree}_{name}"] = {
                     "ms": round(tm, 3), "iters": itv, "setup_s": round(sa_setup, 3),
                     "levels": [amg.amg_level_info(hsa, l) for l in range(amg.amg_num_levels(hsa))]}
             amg.amg_destroy(hsa)

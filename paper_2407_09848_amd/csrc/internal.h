@@ -16,15 +16,19 @@ constexpr int kBlock = 256;   // threads per block for row-parallel kernels (4 w
 constexpr int kMaxChildren = 8;  // 2x2x2 box aggregates
 constexpr int kDenseTile = 64;   // dense coarsest level padded to a multiple of this
 
-// Sliced ELLPACK matrix: rows grouped in slices of 64 (one per lane of a
-// wavefront); inside slice s the entry j of lane l sits at sptr[s] + 64*j + l,
-// so the 64 lanes of a wavefront load consecutive addresses.  Rows shorter
-// than the slice width are padded with (col = row, val = 0).
+// Sliced ELLPACK matrix with G = `group` lanes per row (G in {1, 4, 16, 64}): a
+// slice holds 64 / G rows, one wavefront's worth.  Entry j of row r of slice s
+// sits at sptr[s] + 64 * (j / G) + G * (r % (64 / G)) + j % G, so at every step
+// the 64 lanes of a wavefront load consecutive addresses, and the G lanes of a
+// row then sum their partial products.  G = 1 (one row per lane) suits short
+// rows; long rows (wide coarse stencils) take more lanes.  Rows shorter than
+// the slice width are padded with (col = row, or 0 past the column count; val = 0).
 template <typename T>
 struct Ell {
   int64_t n = 0;
   int64_t nslices = 0;
   int64_t padded = 0;
+  int group = 1;
   int32_t* sptr = nullptr;  // [nslices + 1]
   int32_t* col = nullptr;   // [padded]
   T* val = nullptr;         // [padded]
@@ -273,9 +277,10 @@ int launch_offdiag_ratio(hipStream_t s, int64_t n, const int32_t* ptr, const int
 int validate_csr(hipStream_t s, int64_t n, int64_t nnz, const int32_t* ptr, const int32_t* col, int* flag);
 int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
                    double* minv, int* flag);
-// ncols: number of columns (default n); padding entries use column i when i < ncols, else 0
+// ncols: number of columns (default n); padding entries use column i when i < ncols, else 0.
+// group: lanes per row (1, 4, 16 or 64); 0 chooses from the mean row length
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
-                Ell<double>* out, int64_t ncols = -1);
+                Ell<double>* out, int64_t ncols = -1, int group = 1);
 int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out);
 // box aggregates of edge e; children (2x2x2 boxes only) may be null
 int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int e, int32_t* agg, int32_t* children,

@@ -54,36 +54,41 @@ __global__ void k_l1_diag(int64_t n, const int32_t* __restrict__ ptr, const int3
   minv[i] = 1.0 / m;
 }
 
-// width of every 64-row slice = longest row in it
-__global__ void k_slice_width(int64_t n, int64_t nslices, const int32_t* __restrict__ ptr, int32_t* __restrict__ w) {
+// width of every slice of R rows = longest row in it
+__global__ void k_slice_width(int64_t n, int64_t nslices, int R, const int32_t* __restrict__ ptr,
+                              int32_t* __restrict__ w) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslices) return;
   int m = 0;
-  for (int l = 0; l < kSlice; ++l) {
-    const int64_t i = s * kSlice + l;
+  for (int l = 0; l < R; ++l) {
+    const int64_t i = s * R + l;
     if (i >= n) break;
     m = max(m, ptr[i + 1] - ptr[i]);
   }
   w[s] = m;
 }
 
-__global__ void k_ell_fill(int64_t n, int64_t ncols, int64_t nslices, const int32_t* __restrict__ ptr,
+// one thread per (slice, lane): lane l of slice s serves row s R + l / G, entries j = l % G + G t
+__global__ void k_ell_fill(int64_t n, int64_t ncols, int64_t nslices, int G, const int32_t* __restrict__ ptr,
                            const int32_t* __restrict__ col, const double* __restrict__ val,
                            const int32_t* __restrict__ sptr, int32_t* __restrict__ ecol, double* __restrict__ eval) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nslices * kSlice) return;
-  const int64_t s = i / kSlice;
-  const int lane = (int)(i % kSlice);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslices * kSlice) return;
+  const int64_t s = t / kSlice;
+  const int lane = (int)(t % kSlice);
+  const int64_t i = s * (kSlice / G) + lane / G;
+  const int g = lane % G;
   const int base = sptr[s];
-  const int width = (sptr[s + 1] - base) / kSlice;
+  const int steps = (sptr[s + 1] - base) / kSlice;
   int len = 0, p0 = 0;
   if (i < n) {
     p0 = ptr[i];
     len = ptr[i + 1] - p0;
   }
   const int32_t padcol = (i < n && i < ncols) ? (int32_t)i : 0;
-  for (int j = 0; j < width; ++j) {
-    const int64_t q = base + (int64_t)j * kSlice + lane;
+  for (int st = 0; st < steps; ++st) {
+    const int j = st * G + g;
+    const int64_t q = base + (int64_t)st * kSlice + lane;
     if (j < len) {
       ecol[q] = col[p0 + j];
       eval[q] = val[p0 + j];
@@ -234,14 +239,25 @@ int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* 
 }
 
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
-                Ell<double>* out, int64_t ncols) {
+                Ell<double>* out, int64_t ncols, int group) {
   if (ncols < 0) ncols = n;
+  if (group == 0) {
+    // lanes per row from the mean row length: about four entries or more per lane
+    int32_t last = 0;
+    AMGP_HIP(hipMemcpyAsync(&last, ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AMGP_HIP(hipStreamSynchronize(s));
+    const double mean = (double)last / (double)n;
+    group = mean >= 256 ? 64 : mean >= 64 ? 16 : mean >= 16 ? 4 : 1;
+  }
+  if (group != 1 && group != 4 && group != 16 && group != 64) return AMG_EINVAL;
+  const int R = kSlice / group;
   Ell<double> e;
   e.n = n;
-  e.nslices = (n + kSlice - 1) / kSlice;
+  e.group = group;
+  e.nslices = (n + R - 1) / R;
   int32_t* dw = nullptr;
   AMGP_HIP(hipMalloc(&dw, sizeof(int32_t) * e.nslices));
-  hipLaunchKernelGGL(k_slice_width, dim3(grid_for(e.nslices)), dim3(kBlock), 0, s, n, e.nslices, ptr, dw);
+  hipLaunchKernelGGL(k_slice_width, dim3(grid_for(e.nslices)), dim3(kBlock), 0, s, n, e.nslices, R, ptr, dw);
   std::vector<int32_t> w(e.nslices);
   AMGP_HIP(hipMemcpyAsync(w.data(), dw, sizeof(int32_t) * e.nslices, hipMemcpyDeviceToHost, s));
   AMGP_HIP(hipStreamSynchronize(s));
@@ -250,7 +266,7 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
   int64_t acc = 0;
   for (int64_t i = 0; i < e.nslices; ++i) {
     sp[i] = (int32_t)acc;
-    acc += (int64_t)w[i] * kSlice;
+    acc += (int64_t)((w[i] + group - 1) / group) * kSlice;
     if (acc >= (int64_t)INT32_MAX) return AMG_ECAPACITY;
   }
   sp[e.nslices] = (int32_t)acc;
@@ -259,8 +275,8 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
   if (hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(acc, 1)) != hipSuccess) return AMG_ENOMEM;
   if (hipMalloc(&e.val, sizeof(double) * std::max<int64_t>(acc, 1)) != hipSuccess) return AMG_ENOMEM;
   AMGP_HIP(hipMemcpyAsync(e.sptr, sp.data(), sizeof(int32_t) * (e.nslices + 1), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_ell_fill, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, n, ncols, e.nslices, ptr,
-                     col, val, e.sptr, e.col, e.val);
+  hipLaunchKernelGGL(k_ell_fill, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, n, ncols, e.nslices, group,
+                     ptr, col, val, e.sptr, e.col, e.val);
   AMGP_HIP(hipGetLastError());
   AMGP_HIP(hipStreamSynchronize(s));
   *out = e;
@@ -272,6 +288,7 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
   e.n = a.n;
   e.nslices = a.nslices;
   e.padded = a.padded;
+  e.group = a.group;
   if (hipMalloc(&e.sptr, sizeof(int32_t) * (e.nslices + 1)) != hipSuccess) return AMG_ENOMEM;
   if (hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;
   if (hipMalloc(&e.val, sizeof(float) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;

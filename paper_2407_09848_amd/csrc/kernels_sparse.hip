@@ -9,6 +9,8 @@
 // workgroups round-robin) walks one contiguous range of rows: the neighbours
 // gathered by a row (the previous and next grid lines and planes) were then
 // recently touched by the same XCD and are served from its L2 instead of HBM.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace amgp {
@@ -64,19 +66,46 @@ __device__ __forceinline__ void st(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
-template <bool NT, typename T>
+// Rows with G lanes each (Ell::group): thread t of the grid serves row t / G, and a
+// wavefront covers exactly one slice of 64 / G rows.
+template <int G>
+__device__ __forceinline__ int64_t row_of_thread() {
+  return (logical_block() * kBlock + threadIdx.x) / G;
+}
+
+// True when every row of this wavefront is past n (a uniform exit).  With G > 1 a
+// wavefront whose first row is below n runs whole: its rows past n lie in the padded
+// tail of the last slice (values 0), and every lane takes part in the row sums.
+template <int G>
+__device__ __forceinline__ bool exit_rows(int64_t i, int64_t n) {
+  if constexpr (G == 1) return i >= n;
+  return (logical_block() * kBlock + (threadIdx.x & ~(kWave - 1))) / G >= n;
+}
+
+// (A x)_row; with G > 1 every lane of the row's group returns the sum.
+template <bool NT, int G, typename T>
 __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restrict__ x) {
+  constexpr int R = kSlice / G;
   // every lane of the wavefront is in the same slice: read its bounds once, as scalars
-  const int s = __builtin_amdgcn_readfirstlane((int)(row >> 6));
+  const int s = __builtin_amdgcn_readfirstlane((int)(row / R));
   const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
-  const int lane = (int)(row & 63);
+  const int lane = G == 1 ? (int)(row & 63) : (int)(threadIdx.x & 63);
   T acc = T(0);
 #pragma unroll 4
   for (int p = beg + lane; p < end; p += kSlice) {
     acc += ld<NT>(A.val + p) * x[ld<NT>(A.col + p)];
   }
+  if constexpr (G > 1) {
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  }
   return acc;
+}
+
+// lane 0 of a row's group, on a row below n, does the row's updates
+template <int G>
+__device__ __forceinline__ bool row_owner(int64_t i, int64_t n) {
+  return i < n && (G == 1 || (threadIdx.x & (G - 1)) == 0);
 }
 
 // Wave-level sum with cross-lane shuffles, then across the block's 4 waves via LDS.
@@ -97,20 +126,22 @@ __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // SpMV and residual
 // ---------------------------------------------------------------------------
-template <typename T, bool NT>
+template <typename T, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, EllView<T> A, const T* __restrict__ x,
                                                  T* __restrict__ y) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  st<NT>(y + i, ell_dot<NT>(A, i, x));
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T v = ell_dot<NT, G>(A, i, x);
+  if (row_owner<G>(i, n)) st<NT>(y + i, v);
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  r[i] = ld<NT>(b + i) - ell_dot<NT>(A, i, x);
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T v = ell_dot<NT, G>(A, i, x);
+  if (row_owner<G>(i, n)) r[i] = ld<NT>(b + i) - v;
 }
 
 // ---------------------------------------------------------------------------
@@ -129,16 +160,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 // carries an x update deferred by a first step that gathered x itself.
 // STORE = false on the last step of an application: only x is needed.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool STORE, bool NT>
+template <typename T, int MODE, bool STORE, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                   const T* __restrict__ gold, T* __restrict__ gnew,
                                                   const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
                                                   T wprev, Wt wv, Wt wpv) {
-  const int64_t i = row_index();
-  if (i >= n) return;
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T ag = ell_dot<NT, G>(A, i, gold);
+  if (!row_owner<G>(i, n)) return;
   w = wsel(wv, w, i);
   wprev = wsel(wpv, wprev, i);
-  const T ag = ell_dot<NT>(A, i, gold);
   const T mi = ld<NT>(minv + i);
   const T go = gold[i];
   const T ri = ld<NT>(rin + i);
@@ -185,25 +217,31 @@ __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __res
 // vectors disappears.
 // MODE 0: g1 = c1 M^{-1} b, r1 = b - A g1, g2 = alpha g1 + c M^{-1} r1, x = w1 g1 + w2 g2.
 // MODE 1: r0 = M^{-1} b, d0 = r0 / theta, r1 = r0 - M^{-1} A d0, d1 = alpha d0 + c r1, x = d0 + d1.
-template <typename T, int MODE, bool STORE, bool NT>
+template <typename T, int MODE, bool STORE, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                         const T* __restrict__ b, T* __restrict__ gnew,
                                                         T* __restrict__ r, T* __restrict__ x, T c1, T alpha, T c,
                                                         T w1, T w2, Wt w1v, Wt w2v) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  w1 = wsel(w1v, w1, i);
-  w2 = wsel(w2v, w2, i);
-  const int s = __builtin_amdgcn_readfirstlane((int)(i >> 6));
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  constexpr int R = kSlice / G;
+  const int s = __builtin_amdgcn_readfirstlane((int)(i / R));
   const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
+  const int lane = G == 1 ? (int)(i & 63) : (int)(threadIdx.x & 63);
   T ag = T(0);
 #pragma unroll 4
-  for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
+  for (int p = beg + lane; p < end; p += kSlice) {
     const int j = ld<NT>(A.col + p);
     const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
     ag += ld<NT>(A.val + p) * g1j;
   }
+  if constexpr (G > 1) {
+    for (int off = G / 2; off > 0; off >>= 1) ag += __shfl_xor(ag, off, kWave);
+  }
+  if (!row_owner<G>(i, n)) return;
+  w1 = wsel(w1v, w1, i);
+  w2 = wsel(w2v, w2, i);
   const T mi = minv[i];
   const T bi = b[i];
   T g1, r1, g2;
@@ -228,13 +266,15 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
 // First step from a nonzero x: r^(0) from b - A x.  x is gathered here, so its
 // update is deferred to the next step (or a separate axpy when k = 1).
 // MODE 0: r = b - A x, g = c M^{-1} r.   MODE 1: r = M^{-1}(b - A x), g = r / c (c = theta).
-template <typename T, int MODE, bool NT>
+template <typename T, int MODE, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                       const T* __restrict__ b, const T* __restrict__ x,
                                                       T* __restrict__ r, T* __restrict__ g, T c) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  const T res = ld<NT>(b + i) - ell_dot<NT>(A, i, x);
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T ax = ell_dot<NT, G>(A, i, x);
+  if (!row_owner<G>(i, n)) return;
+  const T res = ld<NT>(b + i) - ax;
   const T mi = ld<NT>(minv + i);
   if (MODE == 0) {
     st<NT>(r + i, res);
@@ -247,13 +287,14 @@ __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, c
 }
 
 // One l1-Jacobi sweep x_new = x_old + M^{-1}(b - A x_old) (eq. l1smooth).
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                    const T* __restrict__ b, const T* __restrict__ xold,
                                                    T* __restrict__ xnew) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  xnew[i] = xold[i] + minv[i] * (b[i] - ell_dot<false>(A, i, xold));
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T ax = ell_dot<false, G>(A, i, xold);
+  if (row_owner<G>(i, n)) xnew[i] = xold[i] + minv[i] * (b[i] - ax);
 }
 
 template <typename T>
@@ -294,12 +335,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t* __
 }
 
 // y += A x for an explicit (smoothed) prolongator in sliced ELL
-template <typename T, bool NT>
+template <typename T, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_spmv_add(int64_t n, EllView<T> A, const T* __restrict__ x,
                                                      T* __restrict__ y) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  y[i] = ld<NT>(y + i) + ell_dot<NT>(A, i, x);
+  const int64_t i = row_of_thread<G>();
+  if (exit_rows<G>(i, n)) return;
+  const T v = ell_dot<NT, G>(A, i, x);
+  if (row_owner<G>(i, n)) y[i] = ld<NT>(y + i) + v;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> 
   const int64_t i = row_index();
   double v = 0.0;
   if (i < n) {
-    const double qi = ell_dot<NT>(A, i, p);
+    const double qi = ell_dot<NT, 1>(A, i, p);
     st<NT>(q + i, qi);
     v = p[i] * qi;
   }
@@ -531,27 +573,50 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(int64_t n, const double
 
 #define LAUNCH_OK() (hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP)
 
-// Levels above kRemapMaxBlocks blocks take the streaming (NT) kernels.
+// Levels above kRemapMaxBlocks blocks take the streaming (NT) kernels (one row per lane).
 inline bool streamed(unsigned grid) { return grid > kRemapMaxBlocks; }
 
-template <typename T>
-int launch_spmv(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
-  const unsigned g = xcd_grid(A.n);
-  if (streamed(g))
-    hipLaunchKernelGGL((k_spmv<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
-  else
-    hipLaunchKernelGGL((k_spmv<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+// Runs f(std::integral_constant<int, G>) for the matrix's lanes per row G.
+template <typename F>
+int with_group(int group, F&& f) {
+  switch (group) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 16: f(std::integral_constant<int, 16>()); break;
+    case 64: f(std::integral_constant<int, 64>()); break;
+    default: return AMG_EINVAL;
+  }
   return LAUNCH_OK();
 }
 
 template <typename T>
+int launch_spmv(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const unsigned g = xcd_grid(A.n * G);
+    if constexpr (G == 1) {
+      if (streamed(g)) {
+        hipLaunchKernelGGL((k_spmv<T, true, 1>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_spmv<T, false, G>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  });
+}
+
+template <typename T>
 int launch_residual(hipStream_t s, const Ell<T>& A, const T* b, const T* x, T* r) {
-  const unsigned g = xcd_grid(A.n);
-  if (streamed(g))
-    hipLaunchKernelGGL((k_residual<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
-  else
-    hipLaunchKernelGGL((k_residual<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
-  return LAUNCH_OK();
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const unsigned g = xcd_grid(A.n * G);
+    if constexpr (G == 1) {
+      if (streamed(g)) {
+        hipLaunchKernelGGL((k_residual<T, true, 1>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_residual<T, false, G>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), b, x, r);
+  });
 }
 
 template <typename T, bool NT>
@@ -579,88 +644,110 @@ int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* m
   return LAUNCH_OK();
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, int G>
 void go_first2_zero(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv,
                     const T* b, T* gnew, T* r, T* x, T a1, T a2, T a3, T a4, T a5, Wt w1v, Wt w2v) {
   dim3 bl(kBlock);
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4, a5,
-                       w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+                       a5, w1v, w2v);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
                        a5, w1v, w2v);
   else if (store)
-    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4, a5,
-                       w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+                       a5, w1v, w2v);
   else
-    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
+    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
                        a5, w1v, w2v);
 }
 
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
                        T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v, Wt w2v) {
-  const dim3 gr(xcd_grid(A.n));
-  if (streamed(gr.x))
-    go_first2_zero<T, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c, (T)w1,
-                            (T)w2, w1v, w2v);
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const dim3 gr(xcd_grid(A.n * G));
+    if constexpr (G == 1) {
+      if (streamed(gr.x)) {
+        go_first2_zero<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c,
+                                   (T)w1, (T)w2, w1v, w2v);
+        return;
+      }
+    }
+    go_first2_zero<T, false, G>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c,
+                                (T)w1, (T)w2, w1v, w2v);
+  });
+}
+
+template <typename T, bool NT, int G>
+void go_first_res(dim3 gr, hipStream_t s, int mode, EllView<T> A, int64_t n, const T* minv, const T* b, const T* x,
+                  T* r, T* g, T c) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_first_res<T, 0, NT, G>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
   else
-    go_first2_zero<T, false>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c, (T)w1,
-                             (T)w2, w1v, w2v);
-  return LAUNCH_OK();
+    hipLaunchKernelGGL((k_first_res<T, 1, NT, G>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
 }
 
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c) {
-  const dim3 gr(xcd_grid(A.n)), bl(kBlock);
-  const bool nt = streamed(gr.x);
-  if (mode == 0 && nt)
-    hipLaunchKernelGGL((k_first_res<T, 0, true>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_first_res<T, 0, false>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
-  else if (nt)
-    hipLaunchKernelGGL((k_first_res<T, 1, true>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
-  else
-    hipLaunchKernelGGL((k_first_res<T, 1, false>), gr, bl, 0, s, A.n, view(A), minv, b, x, r, g, (T)c);
-  return LAUNCH_OK();
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const dim3 gr(xcd_grid(A.n * G));
+    if constexpr (G == 1) {
+      if (streamed(gr.x)) {
+        go_first_res<T, true, 1>(gr, s, mode, view(A), A.n, minv, b, x, r, g, (T)c);
+        return;
+      }
+    }
+    go_first_res<T, false, G>(gr, s, mode, view(A), A.n, minv, b, x, r, g, (T)c);
+  });
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, int G>
 void go_fused(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv, const T* gold,
               T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv) {
   dim3 bl(kBlock);
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_fused<T, 0, true, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+    hipLaunchKernelGGL((k_fused<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
                        wp_, wv, wpv);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_fused<T, 0, false, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+    hipLaunchKernelGGL((k_fused<T, 0, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
                        wp_, wv, wpv);
   else if (store)
-    hipLaunchKernelGGL((k_fused<T, 1, true, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+    hipLaunchKernelGGL((k_fused<T, 1, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
                        wp_, wv, wpv);
   else
-    hipLaunchKernelGGL((k_fused<T, 1, false, NT>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
+    hipLaunchKernelGGL((k_fused<T, 1, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
                        wp_, wv, wpv);
 }
 
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
                  const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv) {
-  const dim3 gr(xcd_grid(A.n));
-  if (streamed(gr.x))
-    go_fused<T, true>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
-                      (T)wprev, wv, wpv);
-  else
-    go_fused<T, false>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
-                       (T)wprev, wv, wpv);
-  return LAUNCH_OK();
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const dim3 gr(xcd_grid(A.n * G));
+    if constexpr (G == 1) {
+      if (streamed(gr.x)) {
+        go_fused<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
+                             (T)wprev, wv, wpv);
+        return;
+      }
+    }
+    go_fused<T, false, G>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
+                          (T)wprev, wv, wpv);
+  });
 }
 
 template <typename T>
 int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew) {
-  hipLaunchKernelGGL(k_jacobi<T>, dim3(xcd_grid(A.n)), dim3(kBlock), 0, s, A.n, view(A), minv, b, xold, xnew);
-  return LAUNCH_OK();
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    hipLaunchKernelGGL((k_jacobi<T, G>), dim3(xcd_grid(A.n * G)), dim3(kBlock), 0, s, A.n, view(A), minv, b, xold,
+                       xnew);
+  });
 }
 
 template <typename T>
@@ -689,12 +776,17 @@ int launch_prolong(hipStream_t s, int64_t n, const int32_t* agg, const T* xc, T*
 
 template <typename T>
 int launch_spmv_add(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
-  const unsigned g = xcd_grid(A.n);
-  if (streamed(g))
-    hipLaunchKernelGGL((k_spmv_add<T, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
-  else
-    hipLaunchKernelGGL((k_spmv_add<T, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
-  return LAUNCH_OK();
+  return with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    const unsigned g = xcd_grid(A.n * G);
+    if constexpr (G == 1) {
+      if (streamed(g)) {
+        hipLaunchKernelGGL((k_spmv_add<T, true, 1>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_spmv_add<T, false, G>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), x, y);
+  });
 }
 
 template <typename T>

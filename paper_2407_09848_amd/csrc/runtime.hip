@@ -574,8 +574,8 @@ int general_level(Handle* h, hipStream_t s, Level& L, Level* C, Csr* Phat) {
   }
   AMGP_TRY(transpose(s, P.c, &PT.c));
   AMGP_TRY(galerkin_general(s, A, P.c, PT.c, &Ac.c, h->dflag));
-  AMGP_TRY(build_ell64(s, P.c.m, P.c.ptr, P.c.col, P.c.val, &L.P64, P.c.ncols));
-  AMGP_TRY(build_ell64(s, PT.c.m, PT.c.ptr, PT.c.col, PT.c.val, &L.PT64, PT.c.ncols));
+  AMGP_TRY(build_ell64(s, P.c.m, P.c.ptr, P.c.col, P.c.val, &L.P64, P.c.ncols, 0));
+  AMGP_TRY(build_ell64(s, PT.c.m, PT.c.ptr, PT.c.col, PT.c.val, &L.PT64, PT.c.ncols, 0));
   C->csr_ptr = Ac.c.ptr;
   C->csr_col = Ac.c.col;
   C->csr_val = Ac.c.val;
@@ -624,7 +624,8 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     int fl[F_NFLAG];
     AMGP_TRY(read_flags(h, s, fl));
     if (fl[F_NOTSPD]) return AMG_ENOTSPD;
-    AMGP_TRY(build_ell64(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, &L.A64));
+    // the fine level keeps one row per lane (the CG kernels read it); coarse levels choose
+    AMGP_TRY(build_ell64(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, &L.A64, -1, h->lv.size() == 1 ? 1 : 0));
     const int64_t per = L.n / h->nbatch;
     if (per <= h->max_coarse) break;
     if (h->aggregation == AMG_AGG_MATCHING) {
