@@ -32,14 +32,21 @@ inline unsigned xcd_grid(int64_t n) {
 // XCD is given the contiguous blocks [x * G/8, (x+1) * G/8), so the
 // neighbouring planes a row gathers were recently touched by the same XCD and
 // hit its L2 (measured: 40.9 vs 44.8 us per fused step at 128^3).  Larger
-// levels stream from HBM and keep the hardware order, in which the 8 XCDs
-// work on nearby rows and share the gathered vector through the MALL
-// (measured: 427 vs 450 us at 256^3, 851 vs 891 us at 320^3).
-// G is a multiple of 8 (xcd_grid).
+// levels stream from HBM: there each XCD takes runs of kXcdChunk consecutive
+// blocks in turn, so that a block's neighbouring grid lines (the adjacent
+// blocks) are mostly on its own XCD, while the neighbouring planes, a multiple
+// of 8 runs away, still are (measured at 256^3: fetched bytes of the fused step
+// -11%, 381 vs 383 us; whole contiguous ranges per XCD: 450 us, since a
+// plane's reuse is then too far away in time).  G is a multiple of 8 (xcd_grid).
 constexpr unsigned kRemapMaxBlocks = 16384;
+constexpr unsigned kXcdChunk = 8;
 
 __device__ __forceinline__ int64_t logical_block() {
-  if (gridDim.x > kRemapMaxBlocks) return blockIdx.x;
+  if (gridDim.x > kRemapMaxBlocks) {
+    if (gridDim.x % (kXcd * kXcdChunk) != 0) return blockIdx.x;
+    const unsigned x = blockIdx.x % kXcd, q = blockIdx.x / kXcd;
+    return (int64_t)(q / kXcdChunk) * (kXcd * kXcdChunk) + x * kXcdChunk + q % kXcdChunk;
+  }
   const unsigned per = gridDim.x / kXcd;
   return (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
 }
@@ -49,21 +56,6 @@ __device__ __forceinline__ int64_t row_index() { return logical_block() * kBlock
 template <typename T>
 __device__ __forceinline__ T wsel(const Wt& w, T scalar, int64_t i) {
   return w.v ? (T)w.v[(int)i / w.rpp * w.stride] : scalar;
-}
-
-// Levels larger than kRemapMaxBlocks blocks stream from HBM: there the matrix
-// and the row-local vectors are read and written with nontemporal hints (NT),
-// which keeps them from displacing the gathered vector in the caches
-// (measured at 256^3: 380 vs 424 us per fused step; on 128^3, whose working
-// set is close to the MALL, the hints cost 15-20%, so smaller levels keep the
-// default policy).  Gathered vectors always use ordinary loads and stores.
-template <bool NT, typename T>
-__device__ __forceinline__ T ld(const T* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
-}
-template <bool NT, typename T>
-__device__ __forceinline__ void st(T* p, T v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
 // Rows with G lanes each (Ell::group): thread t of the grid serves row t / G, and a

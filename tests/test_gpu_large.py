@@ -208,3 +208,53 @@ def test_c2_matching_paper_configuration():
                 assert rc == amg.AMG_OK and tr <= 2e-8, (kind, k, rc, tr)
                 its.append(it)
             _log(f"C2 matching kind {kind}: iterations for k = 1..6: {its}")
+
+
+def test_c5_learned_beta(c5):
+    """The fourth variant of the 27-point workload: learned optimal-4th-kind weights at k = 4.  The
+    network is trained on stacked diffusion problems with the library's own adjoint and network
+    kernels, then applied per level to the 320^3 hierarchy (sigma feature 0, constant coefficients)
+    and kept only if it lowers the two-cycle residual ratio there; the solve must reach 1e-8."""
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    from paper_2407_09848_amd import learned
+    A, b, As = c5
+    nprob, size = 8, 24
+    sig = W.config4_sigmas(nprob)
+    mats = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((size,) * 3, 8.0, W.SEED_GRF + p)))
+            for p in range(nprob)]
+    big = W.stack_block_diagonal(mats)
+    bt = dev(W.rhs_uniform(big.n, W.SEED_RHS + 4))
+    with hierarchy(big, nbatch=nprob, max_coarse=512, precision=amg.AMG_FP32) as ht:
+        res = learned.train(ht, bt, sig, degree=4, steps=60, lr=3e-3, init_params=W.mlp_init(W.SEED_MLP))
+    _log(f"C5 learned: training loss plain {res.plain_loss:.5f}")
+    bd = dev(b)
+    nb = np.linalg.norm(b)
+    with hierarchy(A) as h:
+        L = amg.amg_num_levels(h)
+        lb = learned.learned_level_betas(h, res.params, 4, 0.0)
+        tab = np.array(amg.amg_default_beta(4) * L).reshape(L, 4)
+        tab[:L - 1] = np.array(lb)
+        plain = dev(np.tile(np.array(amg.amg_default_beta(4)), (L, 1)).ravel())
+        r_learned, _ = learned.evaluate(h, dev(tab.ravel()), bd, 4, 1)
+        r_plain, _ = learned.evaluate(h, plain, bd, 4, 1)
+        use = r_learned < r_plain
+        _log(f"C5 learned: two-cycle ratio plain {r_plain:.5f} learned {r_learned:.5f} -> "
+             f"{'learned' if use else 'plain (fallback)'} weights")
+        results = {}
+        for tag in ("plain", "learned"):
+            if tag == "learned" and use:
+                learned.apply_level_betas(h, 4, lb)
+            x = nan_vec(A.n)
+            torch.cuda.synchronize()
+            t = time.time()
+            rc, it, rel, _ = amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 300)
+            torch.cuda.synchronize()
+            dt = time.time() - t
+            tr = np.linalg.norm(b - As @ host(x)) / nb
+            _log(f"C5 {tag}: rc {rc} iters {it} relres {rel:.2e} true {tr:.2e} {dt:.2f} s")
+            assert rc == amg.AMG_OK and tr <= 2e-8
+            results[tag] = it
+        amg.amg_reset_beta(h)
+    if not use:
+        assert results["learned"] == results["plain"]
