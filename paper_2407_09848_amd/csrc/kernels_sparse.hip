@@ -58,6 +58,21 @@ __device__ __forceinline__ T wsel(const Wt& w, T scalar, int64_t i) {
   return w.v ? (T)w.v[(int)i / w.rpp * w.stride] : scalar;
 }
 
+// Levels larger than kRemapMaxBlocks blocks stream from HBM: there the matrix
+// and the row-local vectors are read and written with nontemporal hints (NT),
+// which keeps them from displacing the gathered vector in the caches
+// (measured at 256^3: 380 vs 424 us per fused step; on 128^3, whose working
+// set is close to the MALL, the hints cost 15-20%, so smaller levels keep the
+// default policy).  Gathered vectors always use ordinary loads and stores.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
+
 // Rows with G lanes each (Ell::group): thread t of the grid serves row t / G, and a
 // wavefront covers exactly one slice of 64 / G rows.
 template <int G>
