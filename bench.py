@@ -244,6 +244,11 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     it = iters[-1]
+    # the solve once more, untimed, for its residual history and solution
+    _, _, _, hist = amg.pcg_solve(h, args.kind, args.degree, bd, x, True, 1e-8, 1000, False, True)
+    x_gpu = x.cpu().numpy()
+    solve_info = {"iters": len(hist) - 1, "relres_history": [float(f"{v:.4e}") for v in hist],
+                  "true_relres": float(np.linalg.norm(b - A.to_scipy() @ x_gpu) / np.linalg.norm(b))}
     solve_bytes = pcg_bytes(levels, ncp, 1, args.kind, args.degree, it)
     value = solve_bytes / (ms * 1e-3) / 1e9
 
@@ -372,6 +377,8 @@ def main():
                "sample": f"one full FP64 oracle AMG-PCG solve of the same {args.size}^3 system "
                          f"({res.iters} iterations, {cpu_s:.1f} s, scipy/numpy single thread)",
                "solve_s": round(cpu_s, 2), "iters": res.iters}
+        solve_info["error_vs_oracle"] = float(np.linalg.norm(x_gpu - res.x) / np.linalg.norm(res.x))
+        solve_info["iters_oracle"] = res.iters
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -381,7 +388,8 @@ def main():
                    "smoother": {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}[args.kind],
                    "degree": args.degree, "n": int(n0), "nnz": int(nnz0), "levels": [int(l[0]) for l in levels],
                    "iters": it, "setup_s": round(setup_s, 3)},
-        "roofline": roofline, "cpu_baseline": cpu, "variants": variants, "learned": learned_info,
+        "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
+        "learned": learned_info,
     }
     print(json.dumps(out), flush=True)
 
