@@ -158,7 +158,7 @@ def learned_variant(args, amg, W, h, bd, x, stream, variants):
         nets[deg] = res.params
     for hh in hs:
         amg.amg_destroy(hh)
-    # apply to this system at the bench degree, judged by the two-cycle residual ratio here
+    # apply to this system at the bench degree, kept only if it lowers the two-cycle residual ratio here
     deg = args.degree
     lb = learned.learned_level_betas(h, nets[deg], deg, 0.0)
     L = amg.amg_num_levels(h)

@@ -7,8 +7,8 @@ with the library's hand-written adjoint (amg_train_loss_grad) and its MLP
 forward / backward / Adam kernels.  A predicted weight row whose polynomial
 leaves Pi_k (|p| >= 1 somewhere on (0, 1], eq. polspace) falls back to the
 tabulated weights; the caller can also keep the tabulated weights when the
-network does not lower the loss (the plain optimal-beta smoother is the
-fallback and the judge).
+network does not lower the loss (the plain optimal-beta smoother is both the
+fallback and the yardstick of the network's benefit).
 
 Everything numerical runs in the library's kernels; this module only
 allocates device tensors and sequences the calls.

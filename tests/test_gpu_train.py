@@ -253,6 +253,6 @@ def test_learned_beta_gains_over_plain(amg):
         plain = dev(np.tile(np.array(amg.amg_default_beta(k)), (P_, L2, 1)).ravel())
         l_learned, _ = learned.evaluate(h2, beta2, dev(b2), k, P_)
         l_plain, _ = learned.evaluate(h2, plain, dev(b2), k, P_)
-    final = min(l_learned, l_plain)  # the plain weights are the fallback and the judge
+    final = min(l_learned, l_plain)  # the plain weights are the fallback and the yardstick
     print(f"held out: plain {l_plain:.6f} learned {l_learned:.6f} gain {100 * (1 - l_learned / l_plain):.2f}%")
     assert final <= l_plain
