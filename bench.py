@@ -272,10 +272,19 @@ def main():
     t_fused_ms = (t6 - t2) / 4.0
     fused_bytes = b_fused(nnz0, n0, True)
     achieved = fused_bytes / (t_fused_ms * 1e-3) / 1e9
+    # the bytes the kernel must move in the layout it uses: offset-aligned slices read no column
+    # indices (8 bytes per stored entry plus a 4-byte offset per 64), packed ones 12
+    padded, lanes, aligned = amg.amg_level_layout(h, 0)
+    format_bytes = (8 * padded + 4 * (padded // 64) if aligned else 12 * padded) + 56 * n0
+    achieved_fmt = format_bytes / (t_fused_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM, 4), "traffic": measured_traffic(args.size),
                 "kernel": f"k_fused<double,0,true> (fine level, {args.size}^3)",
-                "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2)}
+                "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2),
+                "layout": {"stored_entries": int(padded), "lanes_per_row": lanes, "offset_aligned": aligned,
+                           "format_bytes_per_launch": int(format_bytes),
+                           "achieved_format": round(achieved_fmt, 1),
+                           "frac_format": round(achieved_fmt / PEAK_HBM, 4)}}
 
     # ---- plain device copy of 1 GiB: measured copy bandwidth, and the reference
     #      dispatch that calibrates the HBM byte counters of a profiling run ----

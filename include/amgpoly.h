@@ -129,6 +129,12 @@ int amg_destroy(amg_handle* h);
 int amg_num_levels(const amg_handle* h, int* h_nlevels);
 int amg_level_info(const amg_handle* h, int level, int64_t* h_n, int64_t* h_nnz);
 
+/* Storage of level l's operator in the kernels' sliced-ELL format (host outputs, any may be
+ * NULL): *h_padded stored entries including padding, *h_lanes lanes per row (1, 4, 16 or
+ * 64), *h_aligned 1 when its slices are offset-aligned (columns formed as row + a per-slice
+ * offset, no column indices read), else 0. */
+int amg_level_layout(const amg_handle* h, int level, int64_t* h_padded, int* h_lanes, int* h_aligned);
+
 /* Copy level l's Galerkin operator (CSR, sorted columns) and its l1 inverse
  * diagonal 1/M_i into caller buffers: d_row_ptr[n+1], d_col[nnz], d_val[nnz],
  * d_minv[n] (float64).  Any pointer may be NULL to skip it.  Asynchronous. */

@@ -14,7 +14,7 @@ AMG_AGG_BOX, AMG_AGG_MATCHING = 0, 1
 AMG_MAX_DEGREE = 12
 
 __all__ = [
-    "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info",
+    "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info", "amg_level_layout",
     "amg_level_export", "amg_default_beta", "amg_default_astar", "amg_set_beta", "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
     "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
@@ -51,6 +51,7 @@ _SIGS = {
     "amg_num_levels": (_I, [_P, ctypes.POINTER(_I)]),
     "amg_level_info": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "amg_level_export": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "amg_level_layout": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "amg_default_beta": (_I, [_I, ctypes.POINTER(_D)]),
     "amg_default_astar": (_I, [_I, ctypes.POINTER(_D)]),
     "amg_set_beta": (_I, [_P, _I, _I, ctypes.POINTER(_D)]),
@@ -153,6 +154,14 @@ def amg_level_info(h, level):
     n, nnz = _I64(), _I64()
     _check(lib().amg_level_info(h, level, ctypes.byref(n), ctypes.byref(nnz)), "amg_level_info")
     return n.value, nnz.value
+
+
+def amg_level_layout(h, level):
+    """(stored entries including padding, lanes per row, offset-aligned) of level l's operator."""
+    padded, lanes, aligned = _I64(), _I(), _I()
+    _check(lib().amg_level_layout(h, level, ctypes.byref(padded), ctypes.byref(lanes), ctypes.byref(aligned)),
+           "amg_level_layout")
+    return padded.value, lanes.value, bool(aligned.value)
 
 
 def amg_level_export(h, level):

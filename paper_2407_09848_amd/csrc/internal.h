@@ -23,6 +23,14 @@ constexpr int kDenseTile = 64;   // dense coarsest level padded to a multiple of
 // row then sum their partial products.  G = 1 (one row per lane) suits short
 // rows; long rows (wide coarse stencils) take more lanes.  Rows shorter than
 // the slice width are padded with (col = row, or 0 past the column count; val = 0).
+//
+// Offset-aligned slices (square matrices with one row per lane): when every
+// slice's rows share few distinct column offsets col - row (stencil matrices),
+// step t of slice s holds the entries of offset doff[sptr[s] / 64 + t] for all
+// its rows (0 where a row has none), so the kernels form the column as
+// row + offset, clamped into [0, n), and read no column indices: 8 instead of
+// 12 bytes per stored FP64 entry.  `col` is still filled (with the same clamped
+// columns) for code that reads it.
 template <typename T>
 struct Ell {
   int64_t n = 0;
@@ -32,6 +40,7 @@ struct Ell {
   int32_t* sptr = nullptr;  // [nslices + 1]
   int32_t* col = nullptr;   // [padded]
   T* val = nullptr;         // [padded]
+  int32_t* doff = nullptr;  // [padded / 64] offsets of offset-aligned slices, or null
 };
 
 // Per-problem smoother weights for stacked problems: the weight of row i is
@@ -47,11 +56,13 @@ struct EllView {
   const int32_t* __restrict__ sptr;
   const int32_t* __restrict__ col;
   const T* __restrict__ val;
+  const int32_t* __restrict__ doff;
+  int32_t last;  // n - 1, the clamp of offset-aligned columns
 };
 
 template <typename T>
 inline EllView<T> view(const Ell<T>& e) {
-  return EllView<T>{e.sptr, e.col, e.val};
+  return EllView<T>{e.sptr, e.col, e.val, e.doff, (int32_t)(e.n - 1)};
 }
 
 // Work vectors of one level in one precision.

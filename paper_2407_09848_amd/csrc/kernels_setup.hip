@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <climits>
+
 #include "internal.h"
 
 namespace amgp {
@@ -96,6 +98,97 @@ __global__ void k_ell_fill(int64_t n, int64_t ncols, int64_t nslices, int G, con
       ecol[q] = padcol;
       eval[q] = 0.0;
     }
+  }
+}
+
+// Distinct column offsets (col - row) of every 64-row slice, sorted: offs[s * 64 + t], count
+// width[s] (-1 when there are more than 64).  One wavefront per slice, an LDS hash set.
+constexpr int kOffHash = 256;
+constexpr int kOffEmpty = INT_MIN;
+
+__global__ __launch_bounds__(kWave) void k_slice_offsets(int64_t n, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col, int32_t* __restrict__ offs,
+                                                         int32_t* __restrict__ width) {
+  __shared__ int set[kOffHash];
+  __shared__ int list[kOffHash];
+  __shared__ int cnt;
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int t = lane; t < kOffHash; t += kWave) set[t] = kOffEmpty;
+  if (lane == 0) cnt = 0;
+  __syncthreads();
+  const int64_t r = s * kSlice + lane;
+  if (r < n) {
+    for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
+      const int o = col[p] - (int)r;
+      unsigned h = ((unsigned)o * 2654435761u) & (kOffHash - 1);
+      for (int probe = 0; probe < kOffHash; ++probe) {
+        const int old = atomicCAS(&set[h], kOffEmpty, o);
+        if (old == kOffEmpty) {
+          atomicAdd(&cnt, 1);
+          break;
+        }
+        if (old == o) break;
+        h = (h + 1) & (kOffHash - 1);
+      }
+    }
+  }
+  __syncthreads();
+  const int c = cnt;
+  if (c > kSlice) {
+    if (lane == 0) width[s] = -1;
+    return;
+  }
+  // compact (slot order), then an odd-even transposition sort of at most 64 values by the wavefront
+  __shared__ int k;
+  if (lane == 0) k = 0;
+  __syncthreads();
+  for (int t = lane; t < kOffHash; t += kWave) {
+    const int v = set[t];
+    if (v != kOffEmpty) list[atomicAdd(&k, 1)] = v;
+  }
+  __syncthreads();
+  for (int phase = 0; phase < c; ++phase) {
+    const int i = 2 * lane + (phase & 1);
+    if (i + 1 < c && list[i] > list[i + 1]) {
+      const int a = list[i];
+      list[i] = list[i + 1];
+      list[i + 1] = a;
+    }
+    __syncthreads();
+  }
+  if (lane < c) offs[s * kSlice + lane] = list[lane];
+  if (lane == 0) width[s] = c;
+}
+
+// Offset-aligned fill: lane l of slice s (row r) puts, at step t, its entry of column r + offs[t]
+// (0 when the row has none); columns are clamped into [0, n).
+__global__ void k_ell_fill_aligned(int64_t n, int64_t nslices, const int32_t* __restrict__ ptr,
+                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                   const int32_t* __restrict__ offs, const int32_t* __restrict__ sptr,
+                                   int32_t* __restrict__ ecol, double* __restrict__ eval, int32_t* __restrict__ doff) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslices * kSlice) return;
+  const int64_t s = t / kSlice;
+  const int lane = (int)(t % kSlice);
+  const int64_t r = s * kSlice + lane;
+  const int base = sptr[s];
+  const int steps = (sptr[s + 1] - base) / kSlice;
+  int p = 0, pe = 0;
+  if (r < n) {
+    p = ptr[r];
+    pe = ptr[r + 1];
+  }
+  for (int st = 0; st < steps; ++st) {
+    const int o = offs[s * kSlice + st];
+    const int64_t c = r + o;
+    double v = 0.0;
+    while (p < pe && col[p] < c) ++p;
+    if (p < pe && col[p] == c) v = val[p++];
+    const int64_t q = base + (int64_t)st * kSlice + lane;
+    ecol[q] = (int32_t)(c < 0 ? 0 : (c > n - 1 ? n - 1 : c));
+    eval[q] = v;
+    if (lane == 0) doff[(base >> 6) + st] = o;
   }
 }
 
@@ -238,6 +331,82 @@ int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* 
   return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
 }
 
+// Offset-aligned sliced ELL (one row per lane) when every slice has at most 64 distinct column
+// offsets and the layout is at most 10% larger than the packed one; AMG_EINVAL otherwise.
+int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                      Ell<double>* out) {
+  const int64_t nslices = (n + kSlice - 1) / kSlice;
+  int32_t *offs = nullptr, *wd = nullptr, *lw = nullptr;
+  auto cleanup = [&]() {
+    hipFree(offs);
+    hipFree(wd);
+    hipFree(lw);
+  };
+  if (hipMalloc(&offs, sizeof(int32_t) * nslices * kSlice) != hipSuccess ||
+      hipMalloc(&wd, sizeof(int32_t) * nslices) != hipSuccess ||
+      hipMalloc(&lw, sizeof(int32_t) * nslices) != hipSuccess) {
+    cleanup();
+    return AMG_ENOMEM;
+  }
+  hipLaunchKernelGGL(k_slice_offsets, dim3((unsigned)nslices), dim3(kWave), 0, s, n, ptr, col, offs, wd);
+  hipLaunchKernelGGL(k_slice_width, dim3(grid_for(nslices)), dim3(kBlock), 0, s, n, nslices, kSlice, ptr, lw);
+  std::vector<int32_t> w(nslices), lwh(nslices);
+  if (hipMemcpyAsync(w.data(), wd, sizeof(int32_t) * nslices, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(lwh.data(), lw, sizeof(int32_t) * nslices, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    cleanup();
+    return AMG_EHIP;
+  }
+  int64_t aligned = 0, packed = 0;
+  for (int64_t i = 0; i < nslices; ++i) {
+    if (w[i] < 0) {
+      cleanup();
+      return AMG_EINVAL;
+    }
+    aligned += (int64_t)w[i] * kSlice;
+    packed += (int64_t)lwh[i] * kSlice;
+  }
+  if (aligned > packed + packed / 10 || aligned >= (int64_t)INT32_MAX) {
+    cleanup();
+    return AMG_EINVAL;
+  }
+  std::vector<int32_t> sp(nslices + 1);
+  int64_t acc = 0;
+  for (int64_t i = 0; i < nslices; ++i) {
+    sp[i] = (int32_t)acc;
+    acc += (int64_t)w[i] * kSlice;
+  }
+  sp[nslices] = (int32_t)acc;
+  Ell<double> e;
+  e.n = n;
+  e.group = 1;
+  e.nslices = nslices;
+  e.padded = acc;
+  if (hipMalloc(&e.sptr, sizeof(int32_t) * (nslices + 1)) != hipSuccess ||
+      hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(acc, 1)) != hipSuccess ||
+      hipMalloc(&e.val, sizeof(double) * std::max<int64_t>(acc, 1)) != hipSuccess ||
+      hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(acc / kSlice, 1)) != hipSuccess) {
+    free_ell(e);
+    cleanup();
+    return AMG_ENOMEM;
+  }
+  int rc = AMG_OK;
+  if (hipMemcpyAsync(e.sptr, sp.data(), sizeof(int32_t) * (nslices + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = AMG_EHIP;
+  if (rc == AMG_OK) {
+    hipLaunchKernelGGL(k_ell_fill_aligned, dim3(grid_for(nslices * kSlice)), dim3(kBlock), 0, s, n, nslices, ptr,
+                       col, val, offs, e.sptr, e.col, e.val, e.doff);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
+  }
+  cleanup();
+  if (rc != AMG_OK) {
+    free_ell(e);
+    return rc;
+  }
+  *out = e;
+  return AMG_OK;
+}
+
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
                 Ell<double>* out, int64_t ncols, int group) {
   if (ncols < 0) ncols = n;
@@ -250,6 +419,10 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
     group = mean >= 256 ? 64 : mean >= 64 ? 16 : mean >= 16 ? 4 : 1;
   }
   if (group != 1 && group != 4 && group != 16 && group != 64) return AMG_EINVAL;
+  if (group == 1 && ncols == n) {
+    const int rc = build_ell_aligned(s, n, ptr, col, val, out);
+    if (rc != AMG_EINVAL) return rc;  // EINVAL: the slices are not offset-aligned; use the packed layout
+  }
   const int R = kSlice / group;
   Ell<double> e;
   e.n = n;
@@ -294,6 +467,10 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
   if (hipMalloc(&e.val, sizeof(float) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;
   AMGP_HIP(hipMemcpyAsync(e.sptr, a.sptr, sizeof(int32_t) * (e.nslices + 1), hipMemcpyDeviceToDevice, s));
   AMGP_HIP(hipMemcpyAsync(e.col, a.col, sizeof(int32_t) * e.padded, hipMemcpyDeviceToDevice, s));
+  if (a.doff) {
+    if (hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(e.padded / kSlice, 1)) != hipSuccess) return AMG_ENOMEM;
+    AMGP_HIP(hipMemcpyAsync(e.doff, a.doff, sizeof(int32_t) * (e.padded / kSlice), hipMemcpyDeviceToDevice, s));
+  }
   hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
   AMGP_HIP(hipGetLastError());
   *out = e;
@@ -304,6 +481,7 @@ void free_ell(Ell<double>& e) {
   hipFree(e.sptr);
   hipFree(e.col);
   hipFree(e.val);
+  hipFree(e.doff);
   e = Ell<double>();
 }
 
@@ -311,6 +489,7 @@ void free_ell(Ell<float>& e) {
   hipFree(e.sptr);
   hipFree(e.col);
   hipFree(e.val);
+  hipFree(e.doff);
   e = Ell<float>();
 }
 

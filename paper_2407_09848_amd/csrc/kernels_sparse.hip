@@ -99,6 +99,17 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
   const int lane = G == 1 ? (int)(row & 63) : (int)(threadIdx.x & 63);
   T acc = T(0);
+  if (G == 1 && A.doff) {
+    // offset-aligned slice: the column is the row plus the step's (uniform) offset
+    const int32_t* off = A.doff + (beg >> 6);
+    const int r = (int)row;
+#pragma unroll 4
+    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
+      const int c = min(max(r + off[t], 0), A.last);
+      acc += ld<NT>(A.val + p) * x[c];
+    }
+    return acc;
+  }
 #pragma unroll 4
   for (int p = beg + lane; p < end; p += kSlice) {
     acc += ld<NT>(A.val + p) * x[ld<NT>(A.col + p)];
@@ -237,11 +248,21 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
   const int lane = G == 1 ? (int)(i & 63) : (int)(threadIdx.x & 63);
   T ag = T(0);
+  if (G == 1 && A.doff) {
+    const int32_t* off = A.doff + (beg >> 6);
 #pragma unroll 4
-  for (int p = beg + lane; p < end; p += kSlice) {
-    const int j = ld<NT>(A.col + p);
-    const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-    ag += ld<NT>(A.val + p) * g1j;
+    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
+      const int j = min(max((int)i + off[t], 0), A.last);
+      const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
+      ag += ld<NT>(A.val + p) * g1j;
+    }
+  } else {
+#pragma unroll 4
+    for (int p = beg + lane; p < end; p += kSlice) {
+      const int j = ld<NT>(A.col + p);
+      const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
+      ag += ld<NT>(A.val + p) * g1j;
+    }
   }
   if constexpr (G > 1) {
     for (int off = G / 2; off > 0; off >>= 1) ag += __shfl_xor(ag, off, kWave);
@@ -436,10 +457,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
     const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
     double acc = 0.0;
+    if (A.doff) {
+      const int32_t* off = A.doff + (beg >> 6);
 #pragma unroll 4
-    for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
-      const int j = ld<NT>(A.col + p);
-      acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
+      for (int p = beg + (int)(i & 63), t = 0; p < end; p += kSlice, ++t) {
+        const int j = min(max((int)i + off[t], 0), A.last);
+        acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
+      }
+    } else {
+#pragma unroll 4
+      for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
+        const int j = ld<NT>(A.col + p);
+        acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
+      }
     }
     const double pi = z[i] + beta * pold[i];
     st<NT>(pnew + i, pi);

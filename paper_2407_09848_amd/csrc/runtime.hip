@@ -898,6 +898,15 @@ int amg_level_info(const amg_handle* h, int level, int64_t* h_n, int64_t* h_nnz)
   return AMG_OK;
 }
 
+int amg_level_layout(const amg_handle* h, int level, int64_t* h_padded, int* h_lanes, int* h_aligned) {
+  if (!h || level < 0 || level >= h->impl.nlevels) return AMG_EINVAL;
+  const amgp::Ell<double>& A = h->impl.lv[level].A64;
+  if (h_padded) *h_padded = A.padded;
+  if (h_lanes) *h_lanes = A.group;
+  if (h_aligned) *h_aligned = A.doff != nullptr;
+  return AMG_OK;
+}
+
 int amg_level_export(const amg_handle* h, int level, int32_t* d_row_ptr, int32_t* d_col, double* d_val,
                      double* d_minv, void* stream) {
   if (!h || level < 0 || level >= h->impl.nlevels) return AMG_EINVAL;

@@ -402,3 +402,54 @@ def test_error_codes(amg):
         with hierarchy(bad):
             pass
     assert ei.value.code == amg.AMG_ENOTSPD
+
+
+def test_storage_layouts(amg):
+    """Stencil levels use offset-aligned slices (no column indices read), dense or irregular rows
+    the packed layout, and wide coarse rows several lanes per row; every layout matches the oracle."""
+    torch = torch_cuda()
+    A = W.poisson3d_7pt(32)
+    with hierarchy(A) as h:
+        for l in range(amg.amg_num_levels(h)):
+            padded, lanes, aligned = amg.amg_level_layout(h, l)
+            assert aligned and lanes == 1, (l, padded, lanes, aligned)
+        padded, _, _ = amg.amg_level_layout(h, 0)
+        # slices hold the offsets their rows use: seven inside, fewer on the boundary planes
+        assert A.nnz <= padded <= 7 * A.n
+    Q, _, _ = W.qdq_dense(256, "equispaced")
+    with hierarchy(Q, max_coarse=4096) as h:
+        padded, lanes, aligned = amg.amg_level_layout(h, 0)
+        assert not aligned and lanes == 1 and padded == 256 * 256
+    with hierarchy(W.poisson3d_7pt(24), max_coarse=100, smoothed=True) as h:
+        lanes = [amg.amg_level_layout(h, l)[1] for l in range(amg.amg_num_levels(h))]
+        assert lanes[0] == 1 and max(lanes[1:]) > 1, lanes
+    # an irregular sparsity pattern (random SPD graph Laplacian): packed layout, smoother parity
+    rng = np.random.default_rng(12)
+    n = 3000
+    G = sp_random_graph(n, 9, rng)
+    with hierarchy(G, max_coarse=4096) as h:
+        assert not amg.amg_level_layout(h, 0)[2]
+        Gs = G.to_scipy()
+        Minv = S.l1_diagonal(Gs)
+        r = rng.uniform(-1, 1, n)
+        for kind in KINDS:
+            x = nan_vec(n)
+            amg.smoother_apply(h, 0, kind, 4, dev(r), x, True)
+            torch.cuda.synchronize()
+            beta, a = oracle_params(kind, 4)
+            assert relerr(host(x), S.smooth(Gs, Minv, r, None, kind, 4, beta, a)) <= 1e-12
+
+
+def sp_random_graph(n, deg, rng):
+    """Graph Laplacian of a random graph plus the identity (SPD, irregular pattern)."""
+    import scipy.sparse as sps
+    rows = np.repeat(np.arange(n), deg)
+    cols = rng.integers(0, n, n * deg)
+    keep = rows != cols
+    Wm = sps.coo_matrix((rng.uniform(0.5, 1.5, keep.sum()), (rows[keep], cols[keep])), shape=(n, n)).tocsr()
+    Wm = (Wm + Wm.T).tocsr()
+    Lap = sps.diags(np.asarray(Wm.sum(axis=1)).ravel() + 1.0) - Wm
+    Lap = Lap.tocsr()
+    Lap.sort_indices()
+    return W.CSR(n=n, row_ptr=Lap.indptr.astype(np.int32), col=Lap.indices.astype(np.int32),
+                 val=Lap.data.astype(np.float64), grid=(n, 1, 1))
