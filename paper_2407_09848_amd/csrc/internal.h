@@ -244,14 +244,11 @@ int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y);
 // CG (float64)
 int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
                 double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
-int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
-                    unsigned* nblocks);
 // p_new = z + beta p_old (beta from scal), q = A p_new, partials of (p_new, q)
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
                       double* pnew, double* q, double* partial, unsigned* nblocks);
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks);
-int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p);
 // pub (optional, RED_RR): receives (r, r) and the breakdown / NaN flags, for the host
 int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag,
                   double* pub = nullptr);

@@ -426,20 +426,6 @@ __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __rest
   }
 }
 
-template <bool NT>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t n, EllView<double> A, const double* __restrict__ p,
-                                                     double* __restrict__ q, double* __restrict__ partial) {
-  const int64_t i = row_index();
-  double v = 0.0;
-  if (i < n) {
-    const double qi = ell_dot<NT, 1>(A, i, p);
-    st<NT>(q + i, qi);
-    v = p[i] * qi;
-  }
-  const double s = block_sum(v);
-  if (threadIdx.x == 0) partial[logical_block()] = s;
-}
-
 // The CG direction update fused into the next SpMV: p_new = z + beta p_old and
 // q = A p_new, with (p_new, q) partials.  p_new of a neighbour is formed on the
 // fly from z and p_old (exactly the value stored for it), so p_new is written
@@ -500,13 +486,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* _
   }
   const double s = block_sum(v);
   if (threadIdx.x == 0) partial[logical_block()] = s;
-}
-
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const double* __restrict__ scal,
-                                                       const double* __restrict__ z, double* __restrict__ p) {
-  const int64_t i = row_index();
-  if (i >= n) return;
-  p[i] = z[i] + scal[S_BETA] * p[i];
 }
 
 // Optional middle stage for long partial lists: block b sums the contiguous chunk b of both
@@ -861,17 +840,6 @@ int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, cons
   return LAUNCH_OK();
 }
 
-int launch_spmv_dot(hipStream_t s, const Ell<double>& A, const double* p, double* q, double* partial,
-                    unsigned* nblocks) {
-  const unsigned g = xcd_grid(A.n);
-  if (streamed(g))
-    hipLaunchKernelGGL(k_spmv_dot<true>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
-  else
-    hipLaunchKernelGGL(k_spmv_dot<false>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), p, q, partial);
-  *nblocks = g;
-  return LAUNCH_OK();
-}
-
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
                       double* pnew, double* q, double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
@@ -893,11 +861,6 @@ int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double*
   else
     hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
   *nblocks = g;
-  return LAUNCH_OK();
-}
-
-int launch_cg_pupdate(hipStream_t s, int64_t n, const double* scal, const double* z, double* p) {
-  hipLaunchKernelGGL(k_cg_pupdate, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, scal, z, p);
   return LAUNCH_OK();
 }
 
