@@ -118,8 +118,9 @@ def smoothed_prolongator(A, Phat, nbatch=1):
 
 
 def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=False, coarse_sweeps=0,
-                    aggregation="box", match_steps=3):
-    """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse.
+                    aggregation="box", match_steps=3, vbm_theta=0.08):
+    """Levels A_0 = A, A_{l+1} = P_l^T A_l P_l while rows per problem > max_coarse
+    (and while the aggregation reduces the level).
 
     ``agg_edge``: edge of the box aggregates; ``smoothed``: use the smoothed
     prolongator; ``coarse_sweeps`` > 0: solve the coarsest level by that many
@@ -127,13 +128,16 @@ def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=Fal
     Outside the default (2x2x2 boxes, plain P) the smoothed P and the Galerkin
     operators pass through drop_small.  ``aggregation="matching"``: aggregates
     from ``match_steps`` compatible weighted matchings (oracle.matching) instead
-    of boxes (one problem only).
+    of boxes (one problem only).  ``aggregation="vbm"``: the classical smoothed
+    aggregation aggregates (oracle.vbm) with strength threshold ``vbm_theta``
+    on level 0, halved on each coarser level (one problem only).
     """
     from .matching import matching_prolongator
-    if aggregation not in ("box", "matching"):
+    from .vbm import vbm_tentative
+    if aggregation not in ("box", "matching", "vbm"):
         raise ValueError(aggregation)
-    if aggregation == "matching" and nbatch != 1:
-        raise ValueError("matching aggregation takes one problem")
+    if aggregation != "box" and nbatch != 1:
+        raise ValueError("graph aggregation takes one problem")
     A = sp.csr_matrix(A)
     A.sort_indices()
     H = Hierarchy(coarse_sweeps=int(coarse_sweeps))
@@ -147,13 +151,17 @@ def build_hierarchy(A, grid, nbatch=1, max_coarse=4096, agg_edge=2, smoothed=Fal
             Pm, wsmooth = matching_prolongator(A, wsmooth, match_steps)
             nc = Pm.shape[1]
             gc = (nc, 1, 1)
+        elif aggregation == "vbm":
+            Pm = vbm_tentative(A, vbm_theta * 0.5 ** (len(H.levels) - 1))
+            nc = Pm.shape[1]
+            gc = (nc, 1, 1)
         else:
             agg, gc = box_aggregates(g, nbatch, agg_edge)
             nc = int(np.prod(gc)) * nbatch
             Pm = prolongator(agg, nc)
         if nc >= A.shape[0]:
-            raise ValueError("aggregation does not reduce the level")
-        general = smoothed or agg_edge != 2 or aggregation == "matching"
+            break  # aggregation no longer reduces the level: this one is the coarsest
+        general = smoothed or agg_edge != 2 or aggregation != "box"
         if smoothed:
             Pm = drop_small(smoothed_prolongator(A, Pm, nbatch))
         Pm.sort_indices()
