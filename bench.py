@@ -338,10 +338,11 @@ def main():
         amg.amg_destroy(h32)
         # the paper's own preconditioner ingredients (Section 4): smoothed prolongator,
         # 30 l1-Jacobi sweeps on the coarsest level, flexible CG
-        # (on the box aggregates and on compatible-matching aggregates of up to 8 rows), and the
+        # (on the box aggregates, on compatible-matching aggregates of up to 8 rows and on the
+        # classical smoothed-aggregation (VBM) aggregates with strength threshold 0.08), and the
         # smoothed prolongator with the dense Cholesky coarsest solve of the plain configuration
         for tag, agg, sweeps in (("box", amg.AMG_AGG_BOX, 30), ("matching", amg.AMG_AGG_MATCHING, 30),
-                                 ("box", amg.AMG_AGG_BOX, 0)):
+                                 ("vbm", amg.AMG_AGG_VBM, 30), ("box", amg.AMG_AGG_BOX, 0)):
             name = f"{tag}_smoothed_p_" + (f"sweeps{sweeps}_fcg" if sweeps else "cholesky_fcg")
             t0 = time.perf_counter()
             try:

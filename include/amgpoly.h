@@ -70,6 +70,7 @@ extern "C" {
 /* ---- aggregation ---- */
 #define AMG_AGG_BOX       0  /* fixed boxes of the structured grid (agg_edge) */
 #define AMG_AGG_MATCHING  1  /* compatible weighted matching (Section 4), one problem only */
+#define AMG_AGG_VBM       2  /* classical smoothed aggregation (Section 4, VBM), one problem only */
 
 /* Highest supported polynomial degree (tabulated constants exist for 1..AMG_MAX_DEGREE). */
 #define AMG_MAX_DEGREE 12
@@ -88,7 +89,7 @@ typedef struct amg_opts {
                             omega = 4 / (3 ||D^{-1} A||_inf) per stacked problem (Section 4) */
   int32_t coarse_sweeps; /* > 0: the coarsest level is solved by this many l1-Jacobi sweeps from
                             zero (at most 1000) instead of the dense Cholesky factorisation */
-  int32_t aggregation;   /* AMG_AGG_BOX (0) or AMG_AGG_MATCHING: aggregates from match_steps
+  int32_t aggregation;   /* AMG_AGG_BOX (0), AMG_AGG_VBM (below) or AMG_AGG_MATCHING: aggregates from match_steps
                             approximate maximum-weight matchings of the graph of A_l, edge weight
                             1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2) for the smooth vector w
                             (ones on level 0, then the coarse one), matched greedily in decreasing
@@ -96,6 +97,18 @@ typedef struct amg_opts {
                             holds w restricted to it, normalised.  Requires nbatch = 1 and a
                             structurally symmetric A; the grid extents are not used then */
   int32_t match_steps;   /* matching steps per level, 1..3 (aggregates of up to 2^steps rows); 0 means 3 */
+  double vbm_theta;      /* AMG_AGG_VBM: strength threshold on level 0, halved on each coarser level
+                            (finite, >= 0; 0 makes every nonzero coupling strong).  The edge {i, j}
+                            is strong when a_ij != 0 and q_ij >= rint(2^30 theta_l^2), where
+                            q_ij = rint(2^30 a_ij^2 / |a_ii a_jj|) with a_ij from the smaller row
+                            (the grid keeps couplings that are equal in exact arithmetic equal).
+                            Roots: the greedy maximal set of vertices pairwise at
+                            least three strong edges apart, in decreasing SplitMix64 order of the
+                            index; a root's aggregate is it and its strong neighbours; every other
+                            vertex joins the aggregate of its aggregated neighbour of largest q_ij
+                            (ties: smaller index); aggregates are numbered by root, the tentative
+                            prolongator is piecewise constant (entries 1.0).  Requires nbatch = 1
+                            and a structurally symmetric A; the grid extents are not used then */
 } amg_opts;
 
 /* ---------------------------------------------------------------------------

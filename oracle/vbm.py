@@ -7,11 +7,14 @@ defers the construction to that reference; restated here, with the points it
 leaves open fixed as follows.
 
 * Strength of connection on level l with threshold theta_l = theta / 2^l (the
-  threshold of the cited method is halved on each coarser level): the edge
-  {i, j}, i != j, is strong when a_ij != 0 and a_ij^2 >= theta_l^2 |a_ii a_jj|
-  (the squared form of |a_ij| >= theta_l sqrt(|a_ii a_jj|)), with a_ij read from
-  the row of the smaller index so that both ends see one decision.  N_i is i
-  with its strong neighbours.
+  threshold of the cited method is halved on each coarser level): the coupling
+  of the edge {i, j}, i != j, is s_ij = a_ij^2 / |a_ii a_jj| (the square of
+  |a_ij| / sqrt(|a_ii a_jj|)), with a_ij read from the row of the smaller index
+  so that both ends see one value.  It is rounded to a grid of 2^-30,
+  q_ij = rint(2^30 s_ij), so that couplings equal in exact arithmetic compare
+  equal although the Galerkin products that made them differ in rounding.  The
+  edge is strong when a_ij != 0 and q_ij >= rint(2^30 theta_l^2).  N_i is i with
+  its strong neighbours.
 * Phase 1 (root neighbourhoods): the vertices are visited in decreasing order of
   the SplitMix64 hash of their index; a vertex whose neighbourhood N_i meets no
   aggregate formed so far becomes a root and N_i its aggregate.  N_i and N_r are
@@ -20,7 +23,7 @@ leaves open fixed as follows.
   graph in that order, and the result does not depend on how the visit is
   scheduled (it equals the rounds of locally first vertices that the GPU runs).
 * Phase 2 (enlargement): a vertex outside every phase-1 aggregate joins the
-  phase-1 aggregate of its strong neighbour j with the largest |a_ij| (ties: the
+  phase-1 aggregate of its strong neighbour j with the largest q_ij (ties: the
   smallest j).  By maximality every such vertex has one.
 * Phase 3 (remainder): whatever is still unassigned forms a singleton (never
   reached when phase 1 is maximal; kept so that every row has an aggregate).
@@ -34,9 +37,11 @@ import scipy.sparse as sp
 
 from .matching import splitmix64
 
+QUANT = 2.0**30
+
 
 def strength_graph(A, theta):
-    """Symmetric boolean strength graph (CSR, no diagonal) and the |a_ij| of its edges."""
+    """Symmetric strength graph (CSR, no diagonal) holding q_ij + 1 for each edge (never zero)."""
     A = sp.csr_matrix(A)
     A.sort_indices()
     n = A.shape[0]
@@ -45,10 +50,11 @@ def strength_graph(A, theta):
     cols = A.indices
     upper = cols > rows
     i, j, a = rows[upper], cols[upper], A.data[upper]
-    t2 = float(theta) * float(theta)
-    strong = (a != 0.0) & (a * a >= t2 * np.abs(d[i] * d[j]))
-    i, j, a = i[strong], j[strong], np.abs(a[strong])
-    S = sp.csr_matrix((np.concatenate([a, a]), (np.concatenate([i, j]), np.concatenate([j, i]))), shape=(n, n))
+    q = np.rint((a * a) / np.abs(d[i] * d[j]) * QUANT)
+    qt = np.rint(float(theta) * float(theta) * QUANT)
+    strong = (a != 0.0) & (q >= qt)
+    i, j, q = i[strong], j[strong], q[strong] + 1.0
+    S = sp.csr_matrix((np.concatenate([q, q]), (np.concatenate([i, j]), np.concatenate([j, i]))), shape=(n, n))
     S.sort_indices()
     return S
 
@@ -57,7 +63,7 @@ def vbm_aggregates(A, theta):
     """Aggregate index of every row (numbered by increasing root) and the number of aggregates."""
     S = strength_graph(A, theta)
     n = S.shape[0]
-    ptr, nbr, mag = S.indptr, S.indices, S.data
+    ptr, nbr, key = S.indptr, S.indices, S.data
 
     def neigh(v):
         return nbr[ptr[v]:ptr[v + 1]]
@@ -82,7 +88,7 @@ def vbm_aggregates(A, theta):
             u = int(nbr[p])
             if owner[u] < 0:
                 continue
-            if best < 0 or mag[p] > mag[best] or (mag[p] == mag[best] and u < int(nbr[best])):
+            if best < 0 or key[p] > key[best] or (key[p] == key[best] and u < int(nbr[best])):
                 best = p
         if best >= 0:
             final[v] = owner[int(nbr[best])]

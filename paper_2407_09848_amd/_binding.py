@@ -10,7 +10,7 @@ AMG_OK, AMG_NOT_CONVERGED = 0, 1
 AMG_EINVAL, AMG_ENOTSPD, AMG_ENOMEM, AMG_EHIP, AMG_EBREAKDOWN, AMG_ENAN, AMG_ECAPACITY = -1, -2, -3, -4, -5, -6, -7
 AMG_L1JAC, AMG_CHEB4, AMG_OPTCHEB4, AMG_OPTCHEB1 = 0, 1, 2, 3
 AMG_FP64, AMG_FP32 = 0, 1
-AMG_AGG_BOX, AMG_AGG_MATCHING = 0, 1
+AMG_AGG_BOX, AMG_AGG_MATCHING, AMG_AGG_VBM = 0, 1, 2
 AMG_MAX_DEGREE = 12
 
 __all__ = [
@@ -23,6 +23,7 @@ __all__ = [
     "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
     "AMG_EBREAKDOWN", "AMG_ENAN", "AMG_ECAPACITY", "AMG_L1JAC", "AMG_CHEB4", "AMG_OPTCHEB4",
     "AMG_OPTCHEB1", "AMG_FP64", "AMG_FP32", "AMG_MAX_DEGREE", "AMG_AGG_BOX", "AMG_AGG_MATCHING",
+    "AMG_AGG_VBM",
 ]
 
 
@@ -30,7 +31,7 @@ class AmgOpts(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("nbatch", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("agg_edge", ctypes.c_int32), ("smoothed", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
-                ("aggregation", ctypes.c_int32), ("match_steps", ctypes.c_int32)]
+                ("aggregation", ctypes.c_int32), ("match_steps", ctypes.c_int32), ("vbm_theta", ctypes.c_double)]
 
 
 class AmgError(RuntimeError):
@@ -126,13 +127,13 @@ def amg_strerror(code: int) -> str:
 
 
 def amg_setup(row_ptr, col, val, nx, ny, nz, nbatch=1, max_coarse=4096, precision=AMG_FP64, agg_edge=2,
-              smoothed=False, coarse_sweeps=0, aggregation=AMG_AGG_BOX, match_steps=3):
+              smoothed=False, coarse_sweeps=0, aggregation=AMG_AGG_BOX, match_steps=3, vbm_theta=0.08):
     """Build the hierarchy for the device CSR matrix (int32 row_ptr/col, float64 val); returns the handle."""
     import torch
     n = row_ptr.numel() - 1
     nnz = col.numel()
     o = AmgOpts(nx, ny, nz, nbatch, max_coarse, precision, agg_edge, int(bool(smoothed)), coarse_sweeps,
-                aggregation, match_steps)
+                aggregation, match_steps, float(vbm_theta))
     h = ctypes.c_void_p()
     rc = lib().amg_setup(n, nnz, _ptr(row_ptr, torch.int32, name="row_ptr"), _ptr(col, torch.int32, name="col"),
                          _ptr(val, torch.float64, nnz, "val"), ctypes.byref(o), _stream(), ctypes.byref(h))

@@ -17,9 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libamgpoly.so")
 ARCH = os.environ.get("AMGP_ARCH", "gfx950")
 
-SOURCES = ["kernels_sparse.hip", "kernels_setup.hip", "kernels_galerkin.hip", "kernels_match.hip", "kernels_dense.hip",
-           "kernels_train.hip",
-           "runtime.hip"]
+SOURCES = ["kernels_sparse.hip", "kernels_setup.hip", "kernels_galerkin.hip", "kernels_match.hip", "kernels_vbm.hip",
+           "kernels_dense.hip", "kernels_train.hip", "runtime.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -154,6 +154,7 @@ struct Handle {
   int coarse_sweeps = 0;  // > 0: l1-Jacobi sweeps instead of the dense coarsest solve
   int aggregation = AMG_AGG_BOX;
   int match_steps = 3;    // matching steps per level (aggregates of up to 2^steps rows)
+  double vbm_theta = 0.0;  // strength threshold of the VBM aggregation on level 0
   std::vector<Level> lv;
   // coarsest level: dense inverse per problem, padded to ncp
   int64_t ncl = 0;   // rows per problem on the coarsest level
@@ -316,6 +317,10 @@ int64_t scan_ptr(hipStream_t s, int64_t m, const int32_t* cnt, int32_t* ptr, int
 int matching_prolongator(hipStream_t s, const Csr& A, const double* w0, int steps, Csr* Phat, double** wnext,
                          int* flag);
 int galerkin_general(hipStream_t s, const Csr& A, const Csr& P, const Csr& PT, Csr* Ac, int* flag);
+// ---- classical smoothed aggregation (kernels_vbm.hip) ----
+// aggregate of every row of A (structurally symmetric, ascending columns) for the strength
+// threshold theta, numbered by increasing root; *nc the number of aggregates
+int vbm_aggregates(hipStream_t s, const Csr& A, double theta, int32_t* agg, int64_t* nc);
 void free_ell(Ell<float>& e);
 
 // ---- dense kernels (kernels_dense.hip) ----

@@ -15,38 +15,15 @@
 //   their smallest vertex; the column of aggregate J holds w_i / nu_J, nu_J = ||w|_J||.
 #include <climits>
 
-#include "internal.h"
+#include "graph.h"
 
 namespace amgp {
 
 namespace {
 
-__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
-
-__device__ __forceinline__ unsigned long long edge_hash(int lo, int hi) {
-  return splitmix64(((unsigned long long)(unsigned)lo << 32) | (unsigned)hi);
-}
-
-// a_{row, c} from a row with ascending columns, or nothing
-__device__ __forceinline__ bool find_entry(const int32_t* ptr, const int32_t* col, const double* val, int row, int c,
-                                           double* out) {
-  int lo = ptr[row], hi = ptr[row + 1] - 1;
-  while (lo <= hi) {
-    const int mid = (lo + hi) >> 1;
-    const int cm = col[mid];
-    if (cm == c) {
-      *out = val[mid];
-      return true;
-    }
-    if (cm < c) lo = mid + 1; else hi = mid - 1;
-  }
-  return false;
-}
+using graph::DevBuf;
+using graph::edge_hash;
+using graph::find_entry;
 
 __global__ void k_diag(int64_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                        const double* __restrict__ val, double* __restrict__ d) {
@@ -162,14 +139,6 @@ struct Hold {
   ~Hold() { free_csr(c); }
 };
 
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  ~DevBuf() { hipFree(p); }
-  int alloc(int64_t count) {
-    return hipMalloc(&p, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) == hipSuccess ? AMG_OK : AMG_ENOMEM;
-  }
-};
 
 // One matching step on A (CSR, ascending columns, structurally symmetric) with smooth vector w.
 int matching_step(hipStream_t s, const Csr& A, const double* w, Csr* P, double** wc, int* flag) {

@@ -594,6 +594,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   h->coarse_sweeps = o->coarse_sweeps;
   h->aggregation = o->aggregation;
   h->match_steps = o->match_steps > 0 ? o->match_steps : 3;
+  h->vbm_theta = o->vbm_theta;
   {
     const char* e = std::getenv("AMGP_NO_GRAPH");
     h->use_graphs = !(e && e[0] == '1');
@@ -645,6 +646,23 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
       C.nx = (int)nc;
       C.wsmooth = wnext;
       const int rc = general_level(h, s, L, &C, &Ph.c);
+      h->lv.push_back(C);  // owned by the handle from here on, also on error
+      if (rc != AMG_OK) return rc;
+      continue;
+    }
+    if (h->aggregation == AMG_AGG_VBM) {
+      // classical smoothed aggregation; the threshold is halved on each coarser level (Section 4)
+      const double th = std::ldexp(h->vbm_theta, -(int)(h->lv.size() - 1));
+      int64_t nc = 0;
+      AMGP_TRY(dalloc(&L.agg, L.n));
+      AMGP_TRY(vbm_aggregates(s, level_csr(L), th, L.agg, &nc));
+      if (nc >= L.n) break;
+      L.nc = nc;
+      L.general = true;
+      Level C;
+      C.n = nc;
+      C.nx = (int)nc;
+      const int rc = general_level(h, s, L, &C, nullptr);
       h->lv.push_back(C);  // owned by the handle from here on, also on error
       if (rc != AMG_OK) return rc;
       continue;
@@ -861,8 +879,10 @@ int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d
   if (o.agg_edge < 0 || o.agg_edge == 1 || o.agg_edge > 4) return AMG_EINVAL;
   if (o.smoothed != 0 && o.smoothed != 1) return AMG_EINVAL;
   if (o.coarse_sweeps < 0 || o.coarse_sweeps > 1000) return AMG_EINVAL;
-  if (o.aggregation != AMG_AGG_BOX && o.aggregation != AMG_AGG_MATCHING) return AMG_EINVAL;
-  if (o.aggregation == AMG_AGG_MATCHING && nb != 1) return AMG_EINVAL;
+  if (o.aggregation != AMG_AGG_BOX && o.aggregation != AMG_AGG_MATCHING && o.aggregation != AMG_AGG_VBM)
+    return AMG_EINVAL;
+  if (o.aggregation != AMG_AGG_BOX && nb != 1) return AMG_EINVAL;
+  if (!(o.vbm_theta >= 0.0) || !std::isfinite(o.vbm_theta)) return AMG_EINVAL;
   if (o.match_steps < 0 || o.match_steps > 3) return AMG_EINVAL;
   amg_handle* h = new (std::nothrow) amg_handle;
   if (!h) return AMG_ENOMEM;

@@ -155,8 +155,9 @@ def test_c3_fp32_vs_fp64_full_size():
 
 def test_aniso_full_size():
     """Anisotropy 2D at 2048 x 2048 elements (4.2M unknowns, the paper's per-GPU share): AMG-PCG
-    to 1e-8 with the box hierarchy and with the paper's ingredients (smoothed prolongator, 30
-    coarse l1-Jacobi sweeps, flexible CG); the true residual is checked with the oracle's SpMV."""
+    to 1e-8 with the box hierarchy and with the paper's ingredients (box, matching or VBM
+    aggregates, smoothed prolongator, 30 coarse l1-Jacobi sweeps, flexible CG); the true residual
+    is checked with the oracle's SpMV."""
     torch = torch_cuda()
     import paper_2407_09848_amd as amg
     t = time.time()
@@ -168,7 +169,9 @@ def test_aniso_full_size():
     import paper_2407_09848_amd as amg_
     for name, opts, flex in (("box", {}, False), ("smoothed+sweeps", dict(smoothed=True, coarse_sweeps=30), True),
                              ("matching+smoothed+sweeps", dict(aggregation=amg_.AMG_AGG_MATCHING, smoothed=True,
-                                                               coarse_sweeps=30), True)):
+                                                               coarse_sweeps=30), True),
+                             ("vbm+smoothed+sweeps", dict(aggregation=amg_.AMG_AGG_VBM, smoothed=True,
+                                                          coarse_sweeps=30), True)):
         t = time.time()
         with hierarchy(A, **opts) as h:
             sizes = [amg.amg_level_info(h, l) for l in range(amg.amg_num_levels(h))]

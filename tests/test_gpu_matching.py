@@ -120,7 +120,7 @@ def test_matching_option_validation(amg):
         with hierarchy(big, nbatch=2, max_coarse=8, aggregation=amg.AMG_AGG_MATCHING):
             pass
     assert e.value.code == amg.AMG_EINVAL
-    for bad in (dict(aggregation=2), dict(aggregation=amg.AMG_AGG_MATCHING, match_steps=4)):
+    for bad in (dict(aggregation=3), dict(aggregation=amg.AMG_AGG_MATCHING, match_steps=4)):
         with pytest.raises(amg.AmgError) as e:
             with hierarchy(W.poisson3d_7pt(6), max_coarse=8, **bad):
                 pass

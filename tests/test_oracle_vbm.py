@@ -6,8 +6,9 @@
 * Brute force on small graphs: the roots are pairwise at least three strong edges apart and every
   vertex is within two of a root; the phase-1 aggregates are exactly the roots' neighbourhoods;
   every other vertex sits with the phase-1 aggregate of its strongest aggregated neighbour.
-* The threshold: equality counts as strong (a chain with diagonal 4 at theta = 1/4), just above it nothing
-  is strong, exact zeros are never strong, and the decision reads a_ij from the smaller row.
+* The threshold: equality counts as strong (a chain with diagonal 4 at theta = 1/4), one step of
+  the 2^-30 grid above it nothing is strong, exact zeros are never strong, the decision reads a_ij
+  from the smaller row, and couplings within rounding of each other compare equal.
 * Closed forms: on the 1D Laplacian the aggregates are intervals of 2 to 5 vertices, and a vertex
   halfway between two roots four apart joins the left one (equal strengths, smaller index); on the
   anisotropic 5-point operator the aggregates stay inside grid lines of the strong direction.
@@ -93,12 +94,14 @@ def test_phase1_roots_equal_parallel_rounds_and_phases_hold(name, A, theta):
 
 def test_threshold_equality_zeros_and_row_choice():
     # the 5-point operator on a 12 x 1 grid: a chain with diagonal 4 and off-diagonal -1 (the
-    # y-couplings go to eliminated boundary nodes), so a^2 = t^2 a_ii a_jj exactly at t = 1/4
+    # y-couplings go to eliminated boundary nodes): a^2 / (a_ii a_jj) = 1/16 = theta^2 at 1/4
     L1 = W.poisson2d_5pt(12, 1).to_scipy()
     assert np.all(L1.diagonal() == 4.0)
-    t_eq = 0.25
-    assert V.strength_graph(L1, t_eq).nnz == 2 * (L1.shape[0] - 1)
-    assert V.strength_graph(L1, np.nextafter(t_eq, 1.0)).nnz == 0
+    S1 = V.strength_graph(L1, 0.25)
+    assert S1.nnz == 2 * (L1.shape[0] - 1) and np.all(S1.data == 2.0**26 + 1)
+    t_up = np.sqrt((2.0**26 + 1) / 2.0**30)  # the next point of the grid
+    assert np.rint(t_up * t_up * 2.0**30) == 2.0**26 + 1
+    assert V.strength_graph(L1, t_up).nnz == 0
     agg, nc = V.vbm_aggregates(L1, 0.3)
     assert nc == L1.shape[0] and np.array_equal(agg, np.arange(nc))
     H = amg.build_hierarchy(L1, (12, 1, 1), max_coarse=2, aggregation="vbm", vbm_theta=0.3)
@@ -107,17 +110,23 @@ def test_threshold_equality_zeros_and_row_choice():
     Q = W.q1_27pt(4).to_scipy()
     nonzero_off = int(((Q != 0).sum()) - Q.shape[0])
     assert V.strength_graph(Q, 0.0).nnz == nonzero_off
-    # a_ij and a_ji that differ in the last bit: the smaller row decides for both ends
+    # a_ij and a_ji that differ beyond the grid: the smaller row decides for both ends
     B = sp.lil_matrix(np.array([[2.0, -1.0, 0.0], [-1.0, 2.0, -1.0], [0.0, -1.0, 2.0]]))
-    B[0, 1] = -0.5
-    B[1, 0] = np.nextafter(-0.5, 0.0)
+    low = -0.5 * (1.0 - 2.0**-20)
+    B[0, 1], B[1, 0] = -0.5, low
     Sb = V.strength_graph(sp.csr_matrix(B), 0.25).toarray()
-    assert Sb[0, 1] and Sb[1, 0]  # 0.25 >= 0.0625 * 4 from row 0
-    B[0, 1] = np.nextafter(-0.5, 0.0)
-    B[1, 0] = -0.5
+    assert Sb[0, 1] and Sb[1, 0]  # 0.25 / 4 = theta^2 from row 0
+    B[0, 1], B[1, 0] = low, -0.5
     Sb = V.strength_graph(sp.csr_matrix(B), 0.25).toarray()
     assert not Sb[0, 1] and not Sb[1, 0]
     assert np.array_equal(Sb, Sb.T)
+    # couplings one ulp apart fall on one grid point: phase 2 then breaks the tie by index
+    C = sp.lil_matrix((3, 3))
+    C.setdiag([2.0, 2.0, 2.0])
+    C[0, 1] = C[1, 0] = -1.0
+    C[1, 2] = C[2, 1] = np.nextafter(-1.0, -2.0)
+    Sc = V.strength_graph(sp.csr_matrix(C), 0.0).toarray()
+    assert Sc[1, 0] == Sc[1, 2]
 
 
 @pytest.mark.parametrize("n", [10, 31, 64, 257])
@@ -178,3 +187,20 @@ def test_vbm_pcg_converges_and_needs_one_problem():
     big = W.stack_block_diagonal([W.poisson3d_7pt(4), W.poisson3d_7pt(4)])
     with pytest.raises(ValueError):
         amg.build_hierarchy(big.to_scipy(), big.grid, nbatch=2, max_coarse=8, aggregation="vbm")
+
+
+def test_aggregates_stable_under_rounding_of_coarse_operators():
+    """Smoothed Galerkin levels hold couplings that are equal in exact arithmetic but differ in
+    rounding; a relative perturbation of one ulp in any entry leaves the aggregates unchanged."""
+    M_ = W.poisson3d_7pt(16)
+    H = amg.build_hierarchy(M_.to_scipy(), M_.grid, max_coarse=40, aggregation="vbm", smoothed=True)
+    assert H.L >= 2
+    rng = np.random.default_rng(0)
+    for l in range(1, H.L + 1):
+        A1 = H.levels[l].A
+        ref = V.vbm_aggregates(A1, 0.08 * 0.5**l)
+        for _ in range(3):
+            B = A1.copy()
+            B.data = B.data * (1.0 + rng.choice([-1.0, 0.0, 1.0], B.data.size) * 2.0**-52)
+            agg, nc = V.vbm_aggregates(B, 0.08 * 0.5**l)
+            assert nc == ref[1] and np.array_equal(agg, ref[0])
