@@ -51,6 +51,15 @@ struct Wt {
   int stride = 0;
 };
 
+// The box prolongation x += P x_c (x_i += x_c[agg_i]) carried into the smoother kernels
+// of the post-smoothing instead of a pass of its own: the first step gathers x + P x_c,
+// the kernel after it adds the row's own term.  agg == nullptr: none.
+template <typename T>
+struct Prol {
+  const int32_t* agg = nullptr;
+  const T* xc = nullptr;
+};
+
 template <typename T>
 struct EllView {
   const int32_t* __restrict__ sptr;
@@ -215,17 +224,17 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
                        Wt w2v = Wt());
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
-                     T* g, double c);
+                     T* g, double c, Prol<T> pr = Prol<T>());  // pr: A.group must be 1
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
                  const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv = Wt(),
-                 Wt wpv = Wt());
+                 Wt wpv = Wt(), Prol<T> pr = Prol<T>());
 template <typename T>
 int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew);
 template <typename T>
 int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x);
 // transfers
-// b_c = P^T (b - A x); tmp (n entries) receives b - A x
+// b_c = P^T (b - A x); tmp (n entries) is scratch (one row per lane matrices do not touch it)
 template <typename T>
 int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
                     const T* x, T* tmp, T* bc);
@@ -235,7 +244,8 @@ template <typename T>
 int launch_spmv_add(hipStream_t s, const Ell<T>& A, const T* x, T* y);  // y += A x
 // vectors
 template <typename T>
-int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av = Wt());  // y += a x
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av = Wt(),
+                Prol<T> pr = Prol<T>());  // y += a x (after y += P x_c)
 template <typename T>
 int launch_copy(hipStream_t s, int64_t n, const T* x, T* y);
 template <typename T>

@@ -182,7 +182,7 @@ template <typename T, int MODE, bool STORE, bool NT, int G>
 __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                   const T* __restrict__ gold, T* __restrict__ gnew,
                                                   const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
-                                                  T wprev, Wt wv, Wt wpv) {
+                                                  T wprev, Wt wv, Wt wpv, Prol<T> pr) {
   const int64_t i = row_of_thread<G>();
   if (exit_rows<G>(i, n)) return;
   const T ag = ell_dot<NT, G>(A, i, gold);
@@ -194,7 +194,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
   const T ri = ld<NT>(rin + i);
   const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
-  st<NT>(x + i, ld<NT>(x + i) + wprev * go + w * g);
+  T xi = ld<NT>(x + i);
+  if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
+  st<NT>(x + i, xi + wprev * go + w * g);
   if (STORE) {
     st<NT>(rout + i, r);
     gnew[i] = g;
@@ -314,6 +316,53 @@ __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, c
   }
 }
 
+// (A (x + P x_c))_row for one row per lane (wave-uniform slice, as ell_dot<NT, 1>): the
+// box prolongation x_j + x_c[agg_j] of every gathered entry, in the arithmetic of k_prolong.
+template <bool NT, typename T>
+__device__ __forceinline__ T ell_dot_prol(EllView<T> A, int64_t row, const T* __restrict__ x, Prol<T> pr) {
+  const int s = __builtin_amdgcn_readfirstlane((int)(row / kSlice));
+  const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
+  const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
+  const int lane = (int)(row & 63);
+  T acc = T(0);
+  if (A.doff) {
+    const int32_t* off = A.doff + (beg >> 6);
+    const int r = (int)row;
+#pragma unroll 4
+    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
+      const int c = min(max(r + off[t], 0), A.last);
+      acc += ld<NT>(A.val + p) * (x[c] + pr.xc[pr.agg[c]]);
+    }
+    return acc;
+  }
+#pragma unroll 4
+  for (int p = beg + lane; p < end; p += kSlice) {
+    const int c = ld<NT>(A.col + p);
+    acc += ld<NT>(A.val + p) * (x[c] + pr.xc[pr.agg[c]]);
+  }
+  return acc;
+}
+
+// k_first_res on x + P x_c (the post-smoothing's first step takes over the prolongation;
+// x itself is left for the next kernel, which adds the row's own x_c term).
+template <typename T, int MODE, bool NT>
+__global__ __launch_bounds__(kBlock) void k_first_res_prol(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                           const T* __restrict__ b, const T* __restrict__ x,
+                                                           Prol<T> pr, T* __restrict__ r, T* __restrict__ g, T c) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const T res = ld<NT>(b + i) - ell_dot_prol<NT>(A, i, x, pr);
+  const T mi = ld<NT>(minv + i);
+  if (MODE == 0) {
+    st<NT>(r + i, res);
+    g[i] = c * (mi * res);
+  } else {
+    const T ri = mi * res;
+    st<NT>(r + i, ri);
+    g[i] = ri / c;
+  }
+}
+
 // One l1-Jacobi sweep x_new = x_old + M^{-1}(b - A x_old) (eq. l1smooth).
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_jacobi(int64_t n, EllView<T> A, const T* __restrict__ minv,
@@ -354,6 +403,55 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t nc, const int32_t* 
   bc[I] = s;
 }
 
+// (A x)_row for a row of any slice: the rows of a wavefront may lie in different slices,
+// so the bounds and offsets are per-lane loads.  Same products in the same order as
+// ell_dot<NT, 1>.
+template <bool NT, typename T>
+__device__ __forceinline__ T ell_dot_any(EllView<T> A, int row, const T* __restrict__ x) {
+  const int s = row >> 6;
+  const int beg = A.sptr[s], end = A.sptr[s + 1];
+  T acc = T(0);
+  if (A.doff) {
+    const int32_t* off = A.doff + (beg >> 6);
+#pragma unroll 4
+    for (int p = beg + (row & 63), t = 0; p < end; p += kSlice, ++t) {
+      const int c = min(max(row + off[t], 0), A.last);
+      acc += ld<NT>(A.val + p) * x[c];
+    }
+    return acc;
+  }
+#pragma unroll 4
+  for (int p = beg + (row & 63); p < end; p += kSlice) acc += ld<NT>(A.val + p) * x[ld<NT>(A.col + p)];
+  return acc;
+}
+
+// b_c = P^T (b - A x) for the box P in one pass (one row per lane levels): eight lanes per
+// aggregate, one per child (ascending, -1 padded), each forming its child's residual; the
+// first lane of the eight adds them in ascending order (the absent ones as +0, which
+// leaves the sum unchanged), the order of k_residual followed by k_restrict.  A wavefront's
+// children form four runs of 16 rows, so its loads are less coalesced than the residual's:
+// on large levels the two-kernel path is faster (measured at 128^3: 36.2 vs 26.0 + 6.8 us
+// on the fine level; one launch saved on 262144 rows, 6.5 vs 5.0 + 4.8 us).
+constexpr int64_t kFusedRestrictMaxRows = 1 << 20;
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void k_res_restrict(int64_t nc, EllView<T> A, const int32_t* __restrict__ ch,
+                                                         const T* __restrict__ b, const T* __restrict__ x,
+                                                         T* __restrict__ bc) {
+  const int64_t t = row_index();
+  const int64_t I = t / kMaxChildren;
+  T res = T(0);
+  if (I < nc) {
+    const int c = ld<NT>(ch + t);
+    if (c >= 0) res = ld<NT>(b + c) - ell_dot_any<NT>(A, c, x);
+  }
+  const int base = (int)(threadIdx.x & (kWave - 1)) & ~(kMaxChildren - 1);
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < kMaxChildren; ++k) sum += __shfl(res, base + k, kWave);
+  if (I < nc && (t & (kMaxChildren - 1)) == 0) bc[I] = sum;
+}
+
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_prolong(int64_t n, const int32_t* __restrict__ agg,
                                                     const T* __restrict__ xc, T* __restrict__ x) {
@@ -376,10 +474,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_add(int64_t n, EllView<T> A, co
 // Vector kernels
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y, Wt av) {
+__global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y, Wt av,
+                                                 Prol<T> pr) {
   const int64_t i = row_index();
   if (i >= n) return;
-  y[i] = y[i] + wsel(av, a, i) * x[i];
+  T yi = y[i];
+  if (pr.agg) yi = yi + pr.xc[pr.agg[i]];
+  y[i] = yi + wsel(av, a, i) * x[i];
 }
 
 template <typename T>
@@ -707,7 +808,26 @@ void go_first_res(dim3 gr, hipStream_t s, int mode, EllView<T> A, int64_t n, con
 
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
-                     T* g, double c) {
+                     T* g, double c, Prol<T> pr) {
+  if (pr.agg) {
+    if (A.group != 1) return AMG_EINVAL;
+    const dim3 gr(xcd_grid(A.n));
+    const T cc = (T)c;
+    if (streamed(gr.x)) {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_first_res_prol<T, 0, true>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g, cc);
+      else
+        hipLaunchKernelGGL((k_first_res_prol<T, 1, true>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g, cc);
+    } else {
+      if (mode == 0)
+        hipLaunchKernelGGL((k_first_res_prol<T, 0, false>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g,
+                           cc);
+      else
+        hipLaunchKernelGGL((k_first_res_prol<T, 1, false>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g,
+                           cc);
+    }
+    return LAUNCH_OK();
+  }
   return with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
     const dim3 gr(xcd_grid(A.n * G));
@@ -723,37 +843,38 @@ int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, co
 
 template <typename T, bool NT, int G>
 void go_fused(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv, const T* gold,
-              T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv) {
+              T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv, Prol<T> pr) {
   dim3 bl(kBlock);
   if (mode == 0 && store)
     hipLaunchKernelGGL((k_fused<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv);
+                       wp_, wv, wpv, pr);
   else if (mode == 0)
     hipLaunchKernelGGL((k_fused<T, 0, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv);
+                       wp_, wv, wpv, pr);
   else if (store)
     hipLaunchKernelGGL((k_fused<T, 1, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv);
+                       wp_, wv, wpv, pr);
   else
     hipLaunchKernelGGL((k_fused<T, 1, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv);
+                       wp_, wv, wpv, pr);
 }
 
 template <typename T>
 int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* gold, T* gnew,
-                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv) {
+                 const T* rin, T* rout, T* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv,
+                 Prol<T> pr) {
   return with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
     const dim3 gr(xcd_grid(A.n * G));
     if constexpr (G == 1) {
       if (streamed(gr.x)) {
         go_fused<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
-                             (T)wprev, wv, wpv);
+                             (T)wprev, wv, wpv, pr);
         return;
       }
     }
     go_fused<T, false, G>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
-                          (T)wprev, wv, wpv);
+                          (T)wprev, wv, wpv, pr);
   });
 }
 
@@ -775,6 +896,15 @@ int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x
 template <typename T>
 int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
                     const T* x, T* tmp, T* bc) {
+  static_assert(kMaxChildren == 8 && kWave % kMaxChildren == 0, "eight lanes per aggregate");
+  if (A.group == 1 && A.n <= kFusedRestrictMaxRows) {
+    const unsigned g = xcd_grid(nc * kMaxChildren);
+    if (streamed(g))
+      hipLaunchKernelGGL((k_res_restrict<T, true>), dim3(g), dim3(kBlock), 0, s, nc, view(A), children, b, x, bc);
+    else
+      hipLaunchKernelGGL((k_res_restrict<T, false>), dim3(g), dim3(kBlock), 0, s, nc, view(A), children, b, x, bc);
+    return LAUNCH_OK();
+  }
   AMGP_TRY(launch_residual<T>(s, A, b, x, tmp));
   hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(nc)), dim3(kBlock), 0, s, nc, children, (const T*)tmp, bc);
   return LAUNCH_OK();
@@ -806,8 +936,8 @@ int launch_spmv_add(hipStream_t s, const Ell<T>& A, const T* x, T* y) {
 }
 
 template <typename T>
-int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av) {
-  hipLaunchKernelGGL(k_axpy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, (T)a, x, y, av);
+int launch_axpy(hipStream_t s, int64_t n, double a, const T* x, T* y, Wt av, Prol<T> pr) {
+  hipLaunchKernelGGL(k_axpy<T>, dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, (T)a, x, y, av, pr);
   return LAUNCH_OK();
 }
 
@@ -892,15 +1022,15 @@ int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
   template int launch_first2_zero<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, T*, T*,    \
                                      double, double, double, double, double, Wt, Wt);                         \
   template int launch_first_res<T>(hipStream_t, int, const Ell<T>&, const T*, const T*, const T*, T*, T*,      \
-                                   double);                                                                   \
+                                   double, Prol<T>);                                                          \
   template int launch_fused<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, const T*, T*, T*,  \
-                               double, double, double, double, Wt, Wt);                                       \
+                               double, double, double, double, Wt, Wt, Prol<T>);                              \
   template int launch_jacobi<T>(hipStream_t, const Ell<T>&, const T*, const T*, const T*, T*);                \
   template int launch_jacobi_zero<T>(hipStream_t, int64_t, const T*, const T*, T*);                           \
   template int launch_restrict<T>(hipStream_t, const Ell<T>&, int64_t, const int32_t*, const T*, const T*, T*, T*); \
   template int launch_prolong<T>(hipStream_t, int64_t, const int32_t*, const T*, T*);                         \
   template int launch_spmv_add<T>(hipStream_t, const Ell<T>&, const T*, T*);                                 \
-  template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*, Wt);                                \
+  template int launch_axpy<T>(hipStream_t, int64_t, double, const T*, T*, Wt, Prol<T>);                                \
   template int launch_copy<T>(hipStream_t, int64_t, const T*, T*);                                           \
   template int launch_fill<T>(hipStream_t, int64_t, T, T*);
 
