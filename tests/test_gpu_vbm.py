@@ -147,3 +147,22 @@ def test_vbm_option_validation(amg):
             with hierarchy(W.poisson3d_7pt(6), max_coarse=8, aggregation=amg.AMG_AGG_VBM, vbm_theta=bad):
                 pass
         assert e.value.code == amg.AMG_EINVAL
+
+
+def test_vbm_fp32_hierarchy(amg):
+    """The FP32 hierarchy on VBM aggregates (smoothed prolongator, swept coarsest level) inside the
+    FP64 flexible CG: the same tolerance on the true residual and an iteration count within one of
+    the FP64 hierarchy's (parity unpinned: no exact FP32 answer exists)."""
+    torch = torch_cuda()
+    A, b = W.anisotropy2d_q1(128)
+    opts = dict(aggregation=amg.AMG_AGG_VBM, smoothed=True, coarse_sweeps=30)
+    its = {}
+    for prec in (amg.AMG_FP64, amg.AMG_FP32):
+        with hierarchy(A, max_coarse=200, precision=prec, **opts) as h:
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, amg.AMG_OPTCHEB4, 4, dev(b), x, True, 1e-8, 1000, True)
+            torch.cuda.synchronize()
+            assert rc == amg.AMG_OK
+            assert np.linalg.norm(b - A.to_scipy() @ host(x)) <= 1.05e-8 * np.linalg.norm(b)
+            its[prec] = it
+    assert abs(its[amg.AMG_FP32] - its[amg.AMG_FP64]) <= 1, its
