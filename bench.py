@@ -186,7 +186,51 @@ def learned_variant(args, amg, W, h, bd, x, stream, variants):
                                            "weights": "learned" if use else "plain (fallback)"}
     out["this_system"] = {"two_cycle_ratio_plain": round(r_plain, 6), "two_cycle_ratio_learned": round(r_learned, 6),
                           "weights_used": "learned" if use else "plain (fallback)", "level_betas": lb}
+    out["heldout_solves"] = heldout_solves(args, amg, W, nets[deg], deg, stream)
     return out
+
+
+def heldout_solves(args, amg, W, params, deg, stream):
+    """Time to 1e-8 on held-out problems of the training family (one 64^3 diffusion problem per
+    sigma, FP64 hierarchy, standard PCG), plain optimal weights against the learned ones (kept only
+    where they lower the two-cycle residual ratio of the problem's right-hand side)."""
+    import numpy as np
+    import torch
+
+    from paper_2407_09848_amd import learned
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    res = {}
+    for idx, sigma in enumerate((0.5, 1.0, 2.0)):
+        M = W.fv_diffusion(np.exp(sigma * W.gaussian_random_field((64, 64, 64), 8.0, W.SEED_GRF + 900 + idx)))
+        b = dev(W.rhs_uniform(M.n, W.SEED_RHS + 90 + idx))
+        hp = amg.amg_setup(dev(M.row_ptr), dev(M.col), dev(M.val), *M.grid, 1, 4096, amg.AMG_FP64)
+        x = torch.zeros(M.n, dtype=torch.float64, device="cuda")
+        L = amg.amg_num_levels(hp)
+        lb = learned.learned_level_betas(hp, params, deg, sigma)
+        tab = np.array(amg.amg_default_beta(deg) * L).reshape(L, deg)
+        tab[:L - 1] = np.array(lb)
+        r_l, _ = learned.evaluate(hp, dev(tab.ravel()), b, deg, 1)
+        r_p, _ = learned.evaluate(hp, dev(np.tile(np.array(amg.amg_default_beta(deg)), (L, 1)).ravel()), b, deg, 1)
+        entry = {"two_cycle_ratio_plain": round(r_p, 6), "two_cycle_ratio_learned": round(r_l, 6)}
+        for name, use in (("plain", False), ("learned", r_l < r_p)):
+            amg.amg_reset_beta(hp)
+            if use:
+                learned.apply_level_betas(hp, deg, lb)
+            amg.pcg_solve(hp, args.kind, deg, b, x, True, 1e-8, 1000)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                rc, itv, _, _ = amg.pcg_solve(hp, args.kind, deg, b, x, True, 1e-8, 1000)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            entry[name] = {"ms": round(e0.elapsed_time(e1) / 3, 3), "iters": itv}
+            if name == "learned":
+                entry[name]["weights"] = "learned" if use else "plain (fallback)"
+        entry["learned_vs_plain"] = round(entry["learned"]["ms"] / entry["plain"]["ms"], 3)
+        amg.amg_destroy(hp)
+        res[f"sigma{sigma}"] = entry
+    return res
 
 
 def main():
