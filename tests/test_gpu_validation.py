@@ -1,0 +1,92 @@
+"""Setup rejects malformed input with AMG_EINVAL instead of reading past it: an empty matrix, grid
+extents that do not multiply to n, and CSR arrays of the declared sizes whose contents break the
+format (row pointers that do not start at 0, end at nnz or increase; column indices out of range,
+unsorted or repeated in a row).  The library validates the pointers before it reads any column
+index, so every case here stays within the arrays it is given."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_util import dev, torch_cuda  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amg():
+    torch_cuda()
+    import paper_2407_09848_amd as amg
+    return amg
+
+
+def _setup(amg, rp, cl, vl, grid):
+    torch = torch_cuda()
+    h = amg.amg_setup(dev(rp.astype(np.int32)), dev(cl.astype(np.int32)), dev(vl.astype(np.float64)), *grid)
+    torch.cuda.synchronize()
+    return h
+
+
+def _cases():
+    A = W.poisson3d_7pt(4)
+    rp, cl, vl = A.row_ptr.astype(np.int64), A.col.astype(np.int64), A.val.copy()
+    n = A.n
+    r5 = int(rp[5])
+
+    def mod(rp_=None, cl_=None):
+        return (rp if rp_ is None else rp_), (cl if cl_ is None else cl_)
+
+    out = {}
+    x = rp.copy()
+    x[0] = 1
+    out["ptr_start"] = mod(rp_=x)
+    x = rp.copy()
+    x[5], x[6] = x[6], x[5]
+    out["ptr_decreasing"] = mod(rp_=x)
+    x = rp.copy()
+    x[n] -= 1
+    out["ptr_end"] = mod(rp_=x)
+    x = rp.copy()
+    x[7] = len(cl) + 3
+    out["ptr_beyond_nnz"] = mod(rp_=x)
+    c = cl.copy()
+    c[r5 + 1] = n
+    out["col_past_n"] = mod(cl_=c)
+    c = cl.copy()
+    c[r5] = -1
+    out["col_negative"] = mod(cl_=c)
+    c = cl.copy()
+    c[r5], c[r5 + 1] = c[r5 + 1], c[r5]
+    out["col_unsorted"] = mod(cl_=c)
+    c = cl.copy()
+    c[r5 + 1] = c[r5]
+    out["col_repeated"] = mod(cl_=c)
+    return A, vl, out
+
+
+@pytest.mark.parametrize("case", ["ptr_start", "ptr_decreasing", "ptr_end", "ptr_beyond_nnz", "col_past_n",
+                                  "col_negative", "col_unsorted", "col_repeated"])
+def test_malformed_csr_is_rejected(amg, case):
+    A, vl, cases = _cases()
+    rp, cl = cases[case]
+    with pytest.raises(amg.AmgError) as e:
+        _setup(amg, rp, cl, vl, A.grid)
+    assert e.value.code == amg.AMG_EINVAL, case
+    # the well-formed matrix still sets up on the same device afterwards
+    h = _setup(amg, A.row_ptr, A.col, vl, A.grid)
+    amg.amg_destroy(h)
+
+
+def test_empty_and_mismatched_extents_are_rejected(amg):
+    A = W.poisson3d_7pt(4)
+    with pytest.raises(amg.AmgError) as e:
+        _setup(amg, np.zeros(1), np.zeros(0), np.zeros(0), (1, 1, 1))
+    assert e.value.code == amg.AMG_EINVAL
+    for grid in ((4, 4, 5), (8, 4, 1), (0, 4, 16)):
+        with pytest.raises(amg.AmgError) as e:
+            _setup(amg, A.row_ptr, A.col, A.val, grid)
+        assert e.value.code == amg.AMG_EINVAL, grid
