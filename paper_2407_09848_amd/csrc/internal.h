@@ -252,11 +252,13 @@ template <typename T>
 int launch_fill(hipStream_t s, int64_t n, T v, T* y);
 template <typename Tin, typename Tout>
 int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y);
-// CG (float64)
-int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
+// CG (float64; the preconditioned vector b, d / z may be the FP32 hierarchy's float output)
+template <typename TZ>
+int launch_dot2(hipStream_t s, int64_t n, const double* a, const TZ* b, const double* c, const TZ* d,
                 double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
 // p_new = z + beta p_old (beta from scal), q = A p_new, partials of (p_new, q)
-int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
+template <typename TZ>
+int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const TZ* z, const double* pold,
                       double* pnew, double* q, double* partial, unsigned* nblocks);
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks);

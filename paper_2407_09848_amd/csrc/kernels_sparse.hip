@@ -508,15 +508,17 @@ __global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restric
 // CG kernels (float64): fused SpMV + dot, update + dot, and a single-block
 // second-stage reduction that also forms the CG scalars on the device.
 // ---------------------------------------------------------------------------
-template <bool NT>
+// b and d may be float (the FP32 hierarchy's preconditioned vector): the conversion to
+// double is exact, so the products are those of a converted copy.
+template <bool NT, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __restrict__ a,
-                                                 const double* __restrict__ b, const double* __restrict__ c,
-                                                 const double* __restrict__ d, double* __restrict__ partial) {
+                                                 const TZ* __restrict__ b, const double* __restrict__ c,
+                                                 const TZ* __restrict__ d, double* __restrict__ partial) {
   const int64_t i = row_index();
   double v = 0.0, u = 0.0;
   if (i < n) {
-    v = ld<NT>(a + i) * ld<NT>(b + i);
-    if (c) u = ld<NT>(c + i) * ld<NT>(d + i);
+    v = ld<NT>(a + i) * (double)ld<NT>(b + i);
+    if (c) u = ld<NT>(c + i) * (double)ld<NT>(d + i);
   }
   const double sv = block_sum(v);
   __syncthreads();
@@ -530,10 +532,10 @@ __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __rest
 // The CG direction update fused into the next SpMV: p_new = z + beta p_old and
 // q = A p_new, with (p_new, q) partials.  p_new of a neighbour is formed on the
 // fly from z and p_old (exactly the value stored for it), so p_new is written
-// to the other buffer of a pair.
-template <bool NT>
+// to the other buffer of a pair.  z may be float (exactly converted, as in k_dot2).
+template <bool NT, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double> A, const double* __restrict__ scal,
-                                                       const double* __restrict__ z, const double* __restrict__ pold,
+                                                       const TZ* __restrict__ z, const double* __restrict__ pold,
                                                        double* __restrict__ pnew, double* __restrict__ q,
                                                        double* __restrict__ partial) {
   const int64_t i = row_index();
@@ -549,13 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
 #pragma unroll 4
       for (int p = beg + (int)(i & 63), t = 0; p < end; p += kSlice, ++t) {
         const int j = min(max((int)i + off[t], 0), A.last);
-        acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
+        acc += ld<NT>(A.val + p) * ((double)z[j] + beta * pold[j]);
       }
     } else {
 #pragma unroll 4
       for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
         const int j = ld<NT>(A.col + p);
-        acc += ld<NT>(A.val + p) * (z[j] + beta * pold[j]);
+        acc += ld<NT>(A.val + p) * ((double)z[j] + beta * pold[j]);
       }
     }
     const double pi = z[i] + beta * pold[i];
@@ -813,18 +815,18 @@ int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, co
     if (A.group != 1) return AMG_EINVAL;
     const dim3 gr(xcd_grid(A.n));
     const T cc = (T)c;
+    const EllView<T> av = view(A);
+    const dim3 bl(kBlock);
     if (streamed(gr.x)) {
       if (mode == 0)
-        hipLaunchKernelGGL((k_first_res_prol<T, 0, true>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g, cc);
+        hipLaunchKernelGGL((k_first_res_prol<T, 0, true>), gr, bl, 0, s, A.n, av, minv, b, x, pr, r, g, cc);
       else
-        hipLaunchKernelGGL((k_first_res_prol<T, 1, true>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g, cc);
+        hipLaunchKernelGGL((k_first_res_prol<T, 1, true>), gr, bl, 0, s, A.n, av, minv, b, x, pr, r, g, cc);
     } else {
       if (mode == 0)
-        hipLaunchKernelGGL((k_first_res_prol<T, 0, false>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g,
-                           cc);
+        hipLaunchKernelGGL((k_first_res_prol<T, 0, false>), gr, bl, 0, s, A.n, av, minv, b, x, pr, r, g, cc);
       else
-        hipLaunchKernelGGL((k_first_res_prol<T, 1, false>), gr, dim3(kBlock), 0, s, A.n, view(A), minv, b, x, pr, r, g,
-                           cc);
+        hipLaunchKernelGGL((k_first_res_prol<T, 1, false>), gr, bl, 0, s, A.n, av, minv, b, x, pr, r, g, cc);
     }
     return LAUNCH_OK();
   }
@@ -959,29 +961,39 @@ int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y) {
   return LAUNCH_OK();
 }
 
-int launch_dot2(hipStream_t s, int64_t n, const double* a, const double* b, const double* c, const double* d,
+template <typename TZ>
+int launch_dot2(hipStream_t s, int64_t n, const double* a, const TZ* b, const double* c, const TZ* d,
                 double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(n);
   if (streamed(g))
-    hipLaunchKernelGGL(k_dot2<true>, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
+    hipLaunchKernelGGL((k_dot2<true, TZ>), dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
   else
-    hipLaunchKernelGGL(k_dot2<false>, dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
+    hipLaunchKernelGGL((k_dot2<false, TZ>), dim3(g), dim3(kBlock), 0, s, n, a, b, c, d, partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
+template int launch_dot2<double>(hipStream_t, int64_t, const double*, const double*, const double*, const double*,
+                                 double*, unsigned*);
+template int launch_dot2<float>(hipStream_t, int64_t, const double*, const float*, const double*, const float*,
+                                double*, unsigned*);
 
-int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const double* z, const double* pold,
+template <typename TZ>
+int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const TZ* z, const double* pold,
                       double* pnew, double* q, double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
   if (streamed(g))
-    hipLaunchKernelGGL(k_spmv_dot_p<true>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
+    hipLaunchKernelGGL((k_spmv_dot_p<true, TZ>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
                        partial);
   else
-    hipLaunchKernelGGL(k_spmv_dot_p<false>, dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
+    hipLaunchKernelGGL((k_spmv_dot_p<false, TZ>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew, q,
                        partial);
   *nblocks = g;
   return LAUNCH_OK();
 }
+template int launch_spmv_dot_p<double>(hipStream_t, const Ell<double>&, const double*, const double*, const double*,
+                                       double*, double*, double*, unsigned*);
+template int launch_spmv_dot_p<float>(hipStream_t, const Ell<double>&, const double*, const float*, const double*,
+                                      double*, double*, double*, unsigned*);
 
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
                      double* r, double* rold, double* partial, unsigned* nblocks) {

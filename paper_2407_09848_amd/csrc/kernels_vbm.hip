@@ -122,7 +122,8 @@ __global__ void k_vbm_out(int64_t n, const int32_t* __restrict__ ptr, const int3
 
 // phase 1: owner[i] = the root whose neighbourhood holds i, or -1
 __global__ void k_vbm_owner(int64_t n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                            const double* __restrict__ mag, const int8_t* __restrict__ st, int32_t* __restrict__ owner) {
+                            const double* __restrict__ mag, const int8_t* __restrict__ st,
+                            int32_t* __restrict__ owner) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int o = st[i] == kRoot ? (int)i : -1;

@@ -296,11 +296,14 @@ int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s) {
   return smooth<T>(h, l, kind, k, b, x, false, s);
 }
 
-int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s) {
+// keep32 (FP32 hierarchy): leave the result in the level-0 float vector v32.x instead of
+// converting it into z (the CG kernels read it there).
+int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s, bool keep32 = false) {
   if (h->precision == AMG_FP32) {
     Vecs<float>& v = h->lv[0].v32;
     AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
     AMGP_TRY(vcycle<float>(h, 0, kind, k, v.b, v.x, s));
+    if (keep32) return AMG_OK;
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
   return vcycle<double>(h, 0, kind, k, r, z, s);
@@ -766,11 +769,18 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   return AMG_OK;
 }
 
-int sum_dot(Handle* h, hipStream_t s, int mode, const double* a, const double* b, const double* c, const double* d,
+template <typename TZ>
+int sum_dot(Handle* h, hipStream_t s, int mode, const double* a, const TZ* b, const double* c, const TZ* d,
             int64_t n) {
   unsigned nb = 0;
-  AMGP_TRY(launch_dot2(s, n, a, b, c, d, h->partial, &nb));
+  AMGP_TRY(launch_dot2<TZ>(s, n, a, b, c, d, h->partial, &nb));
   return launch_reduce(s, mode, nb, h->partial, h->scal, h->dflag);
+}
+
+// The preconditioned vector the CG kernels read: the FP32 hierarchy's own float output
+// (exactly converted inside them), else the float64 z.
+const float* cg_z32(const Handle* h, bool poly) {
+  return h->precision == AMG_FP32 && !poly ? h->lv[0].v32.x : nullptr;
 }
 
 int fetch_scalars(Handle* h, hipStream_t s) {
@@ -787,10 +797,13 @@ int precond_dot(Handle* h, int kind, int k, bool poly, int mode, const double* r
                 hipStream_t s) {
   const int64_t n = h->lv[0].n;
   const GraphEntry key{kind, k, mode, poly, r, z, rold, nullptr};
+  const float* z32 = cg_z32(h, poly);
   return run_graph(h, key, s, [&](hipStream_t cs) {
-    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs) : vcycle_top(h, kind, k, r, z, cs));
-    if (mode == RED_BETA_FLEX) return sum_dot(h, cs, mode, r, z, rold, z, n);
-    return sum_dot(h, cs, mode, r, z, nullptr, nullptr, n);
+    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs) : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr));
+    if (z32) return sum_dot<float>(h, cs, mode, r, z32, mode == RED_BETA_FLEX ? rold : nullptr,
+                                   mode == RED_BETA_FLEX ? z32 : nullptr, n);
+    if (mode == RED_BETA_FLEX) return sum_dot<double>(h, cs, mode, r, z, rold, z, n);
+    return sum_dot<double>(h, cs, mode, r, z, nullptr, nullptr, n);
   });
 }
 
@@ -804,10 +817,11 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   const int64_t n = h->lv[0].n;
   const Ell<double>& A = h->lv[0].A64;
   double *r = h->cg_r, *z = h->cg_z, *p = h->cg_p, *q = h->cg_q, *rold = flex ? h->cg_rold : nullptr;
+  const float* z32 = cg_z32(h, poly_only);
   const int* hflag = reinterpret_cast<const int*>(h->hscal + S_NSCAL);
   AMGP_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int) * F_NFLAG, s));
   AMGP_TRY(launch_check_finite(s, n, b, h->dflag));
-  AMGP_TRY(sum_dot(h, s, RED_BB, b, b, nullptr, nullptr, n));
+  AMGP_TRY(sum_dot<double>(h, s, RED_BB, b, b, nullptr, nullptr, n));
   AMGP_TRY(fetch_scalars(h, s));
   if (hflag[F_NAN]) return AMG_ENAN;
   const double bnorm = std::sqrt(h->hscal[S_BB]);
@@ -825,7 +839,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
     AMGP_TRY(launch_copy<double>(s, n, b, r));
   } else {
     AMGP_TRY(launch_residual<double>(s, A, b, x, r));
-    AMGP_TRY(sum_dot(h, s, RED_RR, r, r, nullptr, nullptr, n));
+    AMGP_TRY(sum_dot<double>(h, s, RED_RR, r, r, nullptr, nullptr, n));
     AMGP_TRY(fetch_scalars(h, s));
     rel0 = std::sqrt(h->hscal[S_RR]) / bnorm;
   }
@@ -839,7 +853,10 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   double rel_prev = rel0, rate = 1.0;
   for (int it = 1; it <= maxit; ++it) {
     unsigned nb = 0;
-    AMGP_TRY(launch_spmv_dot_p(s, A, h->scal, z, pold, p, q, h->partial, &nb));
+    if (z32)
+      AMGP_TRY(launch_spmv_dot_p<float>(s, A, h->scal, z32, pold, p, q, h->partial, &nb));
+    else
+      AMGP_TRY(launch_spmv_dot_p<double>(s, A, h->scal, z, pold, p, q, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_ALPHA, nb, h->partial, h->scal, h->dflag));
     AMGP_TRY(launch_cg_update(s, n, h->scal, p, q, x, r, rold, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag, h->dpub));
