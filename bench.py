@@ -243,6 +243,10 @@ def main():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variants", default="kinds,fp32,paper",
+                    help="comma-separated subset of the variants to time: kinds (the other smoother kinds), "
+                         "fp32 (the FP32 hierarchy), paper (smoothed prolongators on box, matching and VBM "
+                         "aggregates)")
     ap.add_argument("--no-learned", action="store_true", help="skip training the learned-weight network")
     ap.add_argument("--train-steps", type=int, default=100)
     args = ap.parse_args()
@@ -358,6 +362,7 @@ def main():
 
     # ---- variants: other kinds, FP32 hierarchy ----
     variants = {}
+    chosen = set(args.variants.split(","))
     if not args.no_variants:
         def time_solve(handle, kind, k, reps=3, flexible=False):
             solve(handle, kind, k, flexible)
@@ -370,23 +375,25 @@ def main():
             torch.cuda.synchronize()
             return e0.elapsed_time(e1) / reps, itv
         names = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
-        for kind in (0, 1, 2, 3):
+        for kind in ((0, 1, 2, 3) if "kinds" in chosen else (args.kind,)):
             tm, itv = time_solve(h, kind, args.degree)
             variants[f"fp64_{names[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv}
-        h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
-        tm, itv = time_solve(h32, args.kind, args.degree)
-        xr = x.cpu().numpy()
-        variants[f"fp32_{names[args.kind]}_k{args.degree}"] = {
-            "ms": round(tm, 3), "iters": itv,
-            "true_relres": float(np.linalg.norm(b - A.to_scipy() @ xr) / np.linalg.norm(b))}
-        amg.amg_destroy(h32)
+        if "fp32" in chosen:
+            h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
+            tm, itv = time_solve(h32, args.kind, args.degree)
+            xr = x.cpu().numpy()
+            variants[f"fp32_{names[args.kind]}_k{args.degree}"] = {
+                "ms": round(tm, 3), "iters": itv,
+                "true_relres": float(np.linalg.norm(b - A.to_scipy() @ xr) / np.linalg.norm(b))}
+            amg.amg_destroy(h32)
         # the paper's own preconditioner ingredients (Section 4): smoothed prolongator,
         # 30 l1-Jacobi sweeps on the coarsest level, flexible CG
         # (on the box aggregates, on compatible-matching aggregates of up to 8 rows and on the
         # classical smoothed-aggregation (VBM) aggregates with strength threshold 0.08), and the
         # smoothed prolongator with the dense Cholesky coarsest solve of the plain configuration
-        for tag, agg, sweeps in (("box", amg.AMG_AGG_BOX, 30), ("matching", amg.AMG_AGG_MATCHING, 30),
-                                 ("vbm", amg.AMG_AGG_VBM, 30), ("box", amg.AMG_AGG_BOX, 0)):
+        paper = (("box", amg.AMG_AGG_BOX, 30), ("matching", amg.AMG_AGG_MATCHING, 30),
+                 ("vbm", amg.AMG_AGG_VBM, 30), ("box", amg.AMG_AGG_BOX, 0))
+        for tag, agg, sweeps in (paper if "paper" in chosen else ()):
             name = f"{tag}_smoothed_p_" + (f"sweeps{sweeps}_fcg" if sweeps else "cholesky_fcg")
             t0 = time.perf_counter()
             try:
