@@ -103,7 +103,7 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
     // offset-aligned slice: the column is the row plus the step's (uniform) offset
     const int32_t* off = A.doff + (beg >> 6);
     const int r = (int)row;
-#pragma unroll 4
+#pragma unroll 2
     for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(r + off[t], 0), A.last);
       acc += ld<NT>(A.val + p) * x[c];
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   T ag = T(0);
   if (G == 1 && A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
-#pragma unroll 4
+#pragma unroll 2
     for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
       const int j = min(max((int)i + off[t], 0), A.last);
       const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
@@ -328,7 +328,7 @@ __device__ __forceinline__ T ell_dot_prol(EllView<T> A, int64_t row, const T* __
   if (A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
     const int r = (int)row;
-#pragma unroll 4
+#pragma unroll 2
     for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(r + off[t], 0), A.last);
       acc += ld<NT>(A.val + p) * (x[c] + pr.xc[pr.agg[c]]);
@@ -413,7 +413,7 @@ __device__ __forceinline__ T ell_dot_any(EllView<T> A, int row, const T* __restr
   T acc = T(0);
   if (A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
-#pragma unroll 4
+#pragma unroll 2
     for (int p = beg + (row & 63), t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(row + off[t], 0), A.last);
       acc += ld<NT>(A.val + p) * x[c];
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     double acc = 0.0;
     if (A.doff) {
       const int32_t* off = A.doff + (beg >> 6);
-#pragma unroll 4
+#pragma unroll 2
       for (int p = beg + (int)(i & 63), t = 0; p < end; p += kSlice, ++t) {
         const int j = min(max((int)i + off[t], 0), A.last);
         acc += ld<NT>(A.val + p) * ((double)z[j] + beta * pold[j]);
