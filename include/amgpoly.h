@@ -18,8 +18,9 @@
  * 2x2x2 boxes of the structured grid (Section 2, first display); the
  * coarsest level is solved directly (dense Cholesky, factor formed at setup).
  * Setup options give the ingredients of the paper's own runs (Section 4):
- * boxes of another edge, the smoothed prolongator and a coarsest solve by a
- * fixed number of l1-Jacobi sweeps.
+ * boxes of another edge, algebraic aggregates (compatible weighted matching or
+ * the classical smoothed aggregation, VBM), the smoothed prolongator and a
+ * coarsest solve by a fixed number of l1-Jacobi sweeps.
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device (HBM) pointers; pointers named h_* are
@@ -119,18 +120,20 @@ typedef struct amg_opts {
  * n must equal nx*ny*nz*nbatch and A must be symmetric with a positive
  * diagonal (symmetry is the caller's promise; it is not checked).  The
  * library copies what it needs: A may be freed after return.  Builds every
- * level's l1 diagonal, the box aggregates, the Galerkin operators, the
+ * level's l1 diagonal, the aggregates, the Galerkin operators, the
  * sliced-ELL copies used by the kernels and the coarsest factor, and
- * allocates all workspace.  Synchronises `stream`.
- * With agg_edge != 2 or smoothed != 0 the transfers use explicit P and P^T
- * (sliced ELL), built with general sparse products; entries of the smoothed P
- * and of the Galerkin operators whose magnitude is at most 2^-46 times the
- * largest of their row are dropped (exact cancellations up to rounding).
+ * allocates all workspace.  Synchronises `stream`.  Coarsening stops at the
+ * first level with at most max_coarse rows per problem, or where the
+ * aggregation no longer reduces the level.
+ * With agg_edge != 2, smoothed != 0 or a graph aggregation the transfers use
+ * explicit P and P^T (sliced ELL), built with general sparse products; entries
+ * of the smoothed P and of the Galerkin operators whose magnitude is at most
+ * 2^-46 times the largest of their row are dropped (exact cancellations up to
+ * rounding).
  * Errors: AMG_EINVAL (null, n mismatch, nnz < n, a row_ptr that is not monotone from
  * 0 to nnz, a column index out of range or not increasing in its row, an option out
- * of range), AMG_ENOTSPD, AMG_ECAPACITY (a product row with more than 3072 distinct
- * columns),
- * AMG_ENOMEM, AMG_EHIP.  On error *out is NULL.
+ * of range, nbatch > 1 with a graph aggregation), AMG_ENOTSPD, AMG_ECAPACITY (a product
+ * row with more than 3072 distinct columns), AMG_ENOMEM, AMG_EHIP.  On error *out is NULL.
  * ------------------------------------------------------------------------- */
 int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
               const double* d_val, const amg_opts* h_opts, void* stream, amg_handle** out);
