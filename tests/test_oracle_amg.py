@@ -204,3 +204,46 @@ def test_amg_pcg_converges_and_true_residual(kind):
     # iteration counts drop (weakly) with degree
     res6, _ = amg.amg_pcg(A.to_scipy(), b, A.grid, kind, 6, max_coarse=512, H=H)
     assert res6.iters <= res.iters
+
+
+def test_flexible_cg_reduces_to_cg_and_to_pcg():
+    """The flexible (Polak-Ribiere) beta equals the standard one whenever the preconditioner is
+    fixed, because consecutive residuals are then B-orthogonal: with B = I it is scipy's CG, and
+    with the fixed V-cycle it takes the standard PCG's iterations to the same solution."""
+    A = W.poisson3d_7pt(12).to_scipy()
+    b = W.rhs_uniform(A.shape[0], 8)
+    res = amg.pcg(A, b, lambda r: r.copy(), rtol=1e-8, maxit=500, flexible=True)
+    count = [0]
+
+    def cb(xk):
+        count[0] += 1
+    x, info = spla.cg(A, b, rtol=1e-8, atol=0.0, maxiter=500, callback=cb)
+    assert info == 0 and res.converged and res.iters == count[0]
+    assert np.allclose(res.x, x, rtol=1e-9, atol=1e-11)
+    A2, b2, _ = W.config_problem(2, size=20)
+    A2 = A2.to_scipy()
+    H = amg.build_hierarchy(A2, (20, 20, 20), max_coarse=200)
+    std, _ = amg.amg_pcg(A2, b2, (20, 20, 20), S.OPTCHEB4, 3, H=H)
+    flx, _ = amg.amg_pcg(A2, b2, (20, 20, 20), S.OPTCHEB4, 3, H=H, flexible=True)
+    assert std.iters == flx.iters
+    assert np.linalg.norm(flx.x - std.x) <= 1e-9 * np.linalg.norm(std.x)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_flexible_cg_survives_a_varying_preconditioner(seed):
+    """A preconditioner that changes at every application (a random positive rescaling of the
+    Jacobi diagonal) breaks the standard beta, which assumes a fixed one: it does not reach 1e-8
+    in 2000 iterations.  The flexible beta keeps consecutive directions A-orthogonal for any
+    preconditioner and converges."""
+    A = W.poisson3d_7pt(16).to_scipy()
+    b = W.rhs_uniform(A.shape[0], 3)
+    Minv = 1.0 / A.diagonal()
+    out = {}
+    for flexible in (False, True):
+        rng = np.random.default_rng(seed)
+        res = amg.pcg(A, b, lambda r: Minv * rng.uniform(0.3, 1.7, r.size) * r, rtol=1e-8, maxit=2000,
+                      flexible=flexible)
+        out[flexible] = res
+    assert not out[False].converged
+    assert out[True].converged and out[True].iters < 400
+    assert np.linalg.norm(b - A @ out[True].x) <= 1.01e-8 * np.linalg.norm(b)
