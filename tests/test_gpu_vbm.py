@@ -149,13 +149,15 @@ def test_vbm_option_validation(amg):
         assert e.value.code == amg.AMG_EINVAL
 
 
-def test_vbm_fp32_hierarchy(amg):
-    """The FP32 hierarchy on VBM aggregates (smoothed prolongator, swept coarsest level) inside the
-    FP64 flexible CG: the same tolerance on the true residual and an iteration count within one of
-    the FP64 hierarchy's (parity unpinned: no exact FP32 answer exists)."""
+@pytest.mark.parametrize("aggregation", ["vbm", "matching"])
+def test_graph_aggregation_fp32_hierarchy(amg, aggregation):
+    """The FP32 hierarchy on VBM or matching aggregates (smoothed prolongator, swept coarsest level)
+    inside the FP64 flexible CG: the same tolerance on the true residual and an iteration count
+    within one of the FP64 hierarchy's (parity unpinned: no exact FP32 answer exists)."""
     torch = torch_cuda()
     A, b = W.anisotropy2d_q1(128)
-    opts = dict(aggregation=amg.AMG_AGG_VBM, smoothed=True, coarse_sweeps=30)
+    agg = amg.AMG_AGG_VBM if aggregation == "vbm" else amg.AMG_AGG_MATCHING
+    opts = dict(aggregation=agg, smoothed=True, coarse_sweeps=30)
     its = {}
     for prec in (amg.AMG_FP64, amg.AMG_FP32):
         with hierarchy(A, max_coarse=200, precision=prec, **opts) as h:
