@@ -207,23 +207,77 @@ __global__ void k_transpose_scatter(int64_t m, const int32_t* __restrict__ ptr, 
   }
 }
 
-// Sort each row of the transpose by column (the keys of a row are distinct).
-__global__ void k_row_sort(int64_t m, const int32_t* __restrict__ ptr, int32_t* __restrict__ col,
-                           double* __restrict__ val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int b = ptr[i], e = ptr[i + 1];
-  for (int p = b + 1; p < e; ++p) {
+// Sorting the rows of the transpose by column (the keys of a row are distinct, so the result
+// is unique): rows of up to kShortRow entries by one thread each (insertion sort), longer ones
+// by one wavefront each (bitonic network in LDS, up to kSortCap entries).
+constexpr int kShortRow = 64;
+constexpr int kSortCap = 4096;
+
+__device__ void insertion_sort_row(int32_t* __restrict__ col, double* __restrict__ val, int len) {
+  for (int p = 1; p < len; ++p) {
     const int c = col[p];
     const double v = val[p];
     int q = p - 1;
-    while (q >= b && col[q] > c) {
+    while (q >= 0 && col[q] > c) {
       col[q + 1] = col[q];
       val[q + 1] = val[q];
       --q;
     }
     col[q + 1] = c;
     val[q + 1] = v;
+  }
+}
+
+__global__ void k_row_sort(int64_t m, const int32_t* __restrict__ ptr, int32_t* __restrict__ col,
+                           double* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int b = ptr[i], len = ptr[i + 1] - b;
+  if (len <= kShortRow) insertion_sort_row(col + b, val + b, len);
+}
+
+// One wavefront per listed row longer than kShortRow.
+__global__ __launch_bounds__(kWave) void k_row_sort_long(const int32_t* __restrict__ rows,
+                                                         const int32_t* __restrict__ ptr, int32_t* __restrict__ col,
+                                                         double* __restrict__ val) {
+  __shared__ int32_t key[kSortCap];
+  __shared__ double v[kSortCap];
+  const int i = rows[blockIdx.x];
+  const int b = ptr[i], len = ptr[i + 1] - b;
+  const int lane = threadIdx.x;
+  if (len > kSortCap) {
+    if (lane == 0) insertion_sort_row(col + b, val + b, len);
+    return;
+  }
+  int pw = 1;
+  while (pw < len) pw <<= 1;
+  for (int t = lane; t < pw; t += kWave) {
+    key[t] = t < len ? col[b + t] : INT_MAX;
+    v[t] = t < len ? val[b + t] : 0.0;
+  }
+  __syncthreads();
+  for (int size = 2; size <= pw; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = lane; t < pw; t += kWave) {
+        const int u = t ^ stride;
+        if (u > t) {
+          const bool up = (t & size) == 0;
+          const int ka = key[t], kb = key[u];
+          if ((ka > kb) == up) {
+            key[t] = kb;
+            key[u] = ka;
+            const double va = v[t];
+            v[t] = v[u];
+            v[u] = va;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = lane; t < len; t += kWave) {
+    col[b + t] = key[t];
+    val[b + t] = v[t];
   }
 }
 
@@ -457,7 +511,34 @@ int transpose(hipStream_t s, const Csr& a, Csr* t) {
     hipLaunchKernelGGL(k_transpose_scatter, dim3(grid_for(a.m)), dim3(kBlock), 0, s, a.m, a.ptr, a.col, a.val,
                        o.ptr, cnt, o.col, o.val);
     hipLaunchKernelGGL(k_row_sort, dim3(grid_for(o.m)), dim3(kBlock), 0, s, o.m, o.ptr, o.col, o.val);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
+    if (hipGetLastError() != hipSuccess) rc = AMG_EHIP;
+  }
+  if (rc == AMG_OK) {
+    // the rows longer than kShortRow, listed on the host from the row pointers
+    std::vector<int32_t> hp(o.m + 1);
+    std::vector<int32_t> longrows;
+    if (hipMemcpyAsync(hp.data(), o.ptr, sizeof(int32_t) * (o.m + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = AMG_EHIP;
+    } else {
+      for (int64_t i = 0; i < o.m; ++i)
+        if (hp[i + 1] - hp[i] > kShortRow) longrows.push_back((int32_t)i);
+    }
+    if (rc == AMG_OK && !longrows.empty()) {
+      int32_t* drows = nullptr;
+      if (hipMalloc(&drows, sizeof(int32_t) * longrows.size()) != hipSuccess) {
+        rc = AMG_ENOMEM;
+      } else {
+        if (hipMemcpyAsync(drows, longrows.data(), sizeof(int32_t) * longrows.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+          rc = AMG_EHIP;
+        if (rc == AMG_OK)
+          hipLaunchKernelGGL(k_row_sort_long, dim3((unsigned)longrows.size()), dim3(kWave), 0, s, drows, o.ptr, o.col,
+                             o.val);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
+        hipFree(drows);
+      }
+    }
   }
   hipFree(cnt);
   if (rc != AMG_OK) {
