@@ -157,6 +157,12 @@ int amg_level_layout(const amg_handle* h, int level, int64_t* h_padded, int* h_l
 int amg_level_export(const amg_handle* h, int level, int32_t* d_row_ptr, int32_t* d_col,
                      double* d_val, double* d_minv, void* stream);
 
+/* Copy the aggregate index of every row of level l (0 <= l < number of levels - 1) into
+ * d_agg[n_l] (int32): the coarse row of level l+1 that the row's tentative prolongator
+ * column belongs to (box, VBM or, for compatible matching, the composite of the matching
+ * steps).  Asynchronous.  AMG_EINVAL for the coarsest level or a null pointer. */
+int amg_level_aggregates(const amg_handle* h, int level, int32_t* d_agg, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Polynomial coefficients (Section 2.1, eq. polsmootheropt; Section 2.3, eq. optimalparameter).
  * The tables are computed offline and compiled in (the paper tabulates them too).

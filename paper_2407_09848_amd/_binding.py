@@ -15,7 +15,8 @@ AMG_MAX_DEGREE = 12
 
 __all__ = [
     "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info", "amg_level_layout",
-    "amg_level_export", "amg_default_beta", "amg_default_astar", "amg_set_beta", "amg_reset_beta",
+    "amg_level_export", "amg_level_aggregates", "amg_default_beta", "amg_default_astar", "amg_set_beta",
+    "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
     "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
     "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_adam",
@@ -52,6 +53,7 @@ _SIGS = {
     "amg_num_levels": (_I, [_P, ctypes.POINTER(_I)]),
     "amg_level_info": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "amg_level_export": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "amg_level_aggregates": (_I, [_P, _I, _P, _P]),
     "amg_level_layout": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "amg_default_beta": (_I, [_I, ctypes.POINTER(_D)]),
     "amg_default_astar": (_I, [_I, ctypes.POINTER(_D)]),
@@ -176,6 +178,15 @@ def amg_level_export(h, level):
     mi = torch.empty(n, dtype=torch.float64, device=dev)
     _check(lib().amg_level_export(h, level, _ptr(rp), _ptr(cl), _ptr(vl), _ptr(mi), _stream()), "amg_level_export")
     return rp, cl, vl, mi
+
+
+def amg_level_aggregates(h, level):
+    """Aggregate index (int32, on the device) of every row of level l, l below the coarsest."""
+    import torch
+    n, _ = amg_level_info(h, level)
+    agg = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(lib().amg_level_aggregates(h, level, _ptr(agg), _stream()), "amg_level_aggregates")
+    return agg
 
 
 def amg_default_beta(degree):

@@ -656,6 +656,11 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
         hipFree(wnext);
         break;
       }
+      // the composite tentative prolongator has one entry per row: its column is the row's aggregate
+      if (Ph.c.nnz == L.n) {
+        AMGP_TRY(dalloc(&L.agg, L.n));
+        AMGP_HIP(hipMemcpyAsync(L.agg, Ph.c.col, sizeof(int32_t) * L.n, hipMemcpyDeviceToDevice, s));
+      }
       L.nc = nc;
       L.general = true;
       Level C;
@@ -967,6 +972,14 @@ int amg_level_export(const amg_handle* h, int level, int32_t* d_row_ptr, int32_t
   if (d_col) AMGP_HIP(hipMemcpyAsync(d_col, L.csr_col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, s));
   if (d_val) AMGP_HIP(hipMemcpyAsync(d_val, L.csr_val, sizeof(double) * L.nnz, hipMemcpyDeviceToDevice, s));
   if (d_minv) AMGP_HIP(hipMemcpyAsync(d_minv, L.v64.minv, sizeof(double) * L.n, hipMemcpyDeviceToDevice, s));
+  return AMG_OK;
+}
+
+int amg_level_aggregates(const amg_handle* h, int level, int32_t* d_agg, void* stream) {
+  if (!h || !d_agg || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;
+  const amgp::Level& L = h->impl.lv[level];
+  if (!L.agg) return AMG_EINVAL;
+  AMGP_HIP(hipMemcpyAsync(d_agg, L.agg, sizeof(int32_t) * L.n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return AMG_OK;
 }
 

@@ -60,3 +60,24 @@ def oracle_params(kind, k):
     beta = P.optimal_beta(k)[0] if kind == 2 else None
     a = P.a_star(k) if kind == 3 else None
     return beta, a
+
+
+def oracle_aggregates(H, aggregation, opts):
+    """Aggregate index of every row of each non-coarsest level of the oracle hierarchy H, as the
+    oracle builds them (box, VBM, or the composite of the matching steps)."""
+    from oracle import amg as OA
+    from oracle import matching as OM
+    from oracle import vbm as OV
+    out = []
+    w = None
+    for l, lv in enumerate(H.levels[:-1]):
+        if aggregation == "box":
+            agg, _ = OA.box_aggregates(lv.grid, lv.nbatch, opts.get("agg_edge", 2))
+        elif aggregation == "vbm":
+            agg, _ = OV.vbm_aggregates(lv.A, opts.get("vbm_theta", 0.08) * 0.5**l)
+        else:
+            Pm, w = OM.matching_prolongator(lv.A, w, opts.get("match_steps", 3))
+            assert np.all(np.diff(Pm.indptr) == 1)
+            agg = Pm.indices
+        out.append(np.asarray(agg, dtype=np.int64))
+    return out

@@ -2,9 +2,9 @@
 matching / VBM aggregates, plain or smoothed prolongator, box edge, matching steps, strength
 threshold, Cholesky or swept coarsest level, polynomial kind and degree 1..12.
 
-Each seeded case checks, at the bars of the dedicated tests: the level sizes and the Galerkin
-sparsity bit-exact, the coarse values within 1e-13 of the largest entry, two V-cycles within 1e-12,
-and the PCG iteration count exactly (a count one apart is accepted only when the oracle's residual
+Each seeded case checks, at the bars of the dedicated tests: the aggregate of every row, the
+level sizes and the Galerkin sparsity bit-exact, the coarse values within 1e-13 of the largest
+entry, two V-cycles within 1e-12, and the PCG iteration count exactly (a count one apart is accepted only when the oracle's residual
 at the stopping test lies within 1e-6 of the tolerance, the borderline reading of the stopping rule).
 """
 import os
@@ -15,7 +15,7 @@ import pytest
 import scipy.sparse as sp
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_util import dev, hierarchy, host, nan_vec, oracle_params, relerr, torch_cuda  # noqa: E402
+from gpu_util import dev, hierarchy, host, nan_vec, oracle_aggregates, oracle_params, relerr, torch_cuda  # noqa: E402
 
 import workloads as W  # noqa: E402
 from oracle import amg as OA  # noqa: E402
@@ -95,6 +95,8 @@ def test_sweep_case_matches_oracle(amg, seed):
     with hierarchy(A, max_coarse=mc, **_lib_opts(amg, agg, opts)) as h:
         sizes = [amg.amg_level_info(h, l)[0] for l in range(amg.amg_num_levels(h))]
         assert sizes == [lv.A.shape[0] for lv in H.levels], tag
+        for l, oagg in enumerate(oracle_aggregates(H, agg, opts)):
+            assert np.array_equal(host(amg.amg_level_aggregates(h, l)).astype(np.int64), oagg), (tag, l)
         for l, lv in enumerate(H.levels):
             rp, cl, vl, _ = amg.amg_level_export(h, l)
             torch.cuda.synchronize()

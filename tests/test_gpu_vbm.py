@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_util import KINDS, dev, hierarchy, host, nan_vec, oracle_params, relerr, torch_cuda  # noqa: E402
+from gpu_util import KINDS, dev, hierarchy, host, nan_vec, oracle_aggregates, oracle_params, relerr, torch_cuda  # noqa: E402,E501
 
 import workloads as W  # noqa: E402
 from oracle import amg as OA  # noqa: E402
@@ -58,6 +58,8 @@ def test_vbm_hierarchy_matches_oracle(amg, case, smoothed):
     with hierarchy(A, max_coarse=mc, aggregation=amg.AMG_AGG_VBM, smoothed=smoothed, vbm_theta=th) as h:
         sizes = [amg.amg_level_info(h, l)[0] for l in range(amg.amg_num_levels(h))]
         assert sizes == [lv.A.shape[0] for lv in H.levels], (case, sizes)
+        for l, oagg in enumerate(oracle_aggregates(H, "vbm", dict(vbm_theta=th))):
+            assert np.array_equal(host(amg.amg_level_aggregates(h, l)).astype(np.int64), oagg), (case, l)
         for l, lv in enumerate(H.levels):
             rp, cl, vl, mi = amg.amg_level_export(h, l)
             torch.cuda.synchronize()
