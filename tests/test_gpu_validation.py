@@ -90,3 +90,50 @@ def test_empty_and_mismatched_extents_are_rejected(amg):
         with pytest.raises(amg.AmgError) as e:
             _setup(amg, A.row_ptr, A.col, A.val, grid)
         assert e.value.code == amg.AMG_EINVAL, grid
+
+
+def test_calls_follow_the_callers_stream(amg):
+    """Every call enqueues on the caller's current stream (torch's, here a side stream of default
+    priority): input written on that stream just before the call, behind a long matrix product,
+    is what the call reads, with no synchronisation in between; the results equal those of the
+    same calls on the default stream bitwise."""
+    torch = torch_cuda()
+    A, b, _ = W.config_problem(2, size=32)
+    src = dev(b)
+    with _hier(amg, A) as h:
+        z_ref = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        amg.vcycle_apply(h, 2, 4, src, z_ref)
+        x_ref = torch.empty_like(z_ref)
+        rc, it_ref, _, _ = amg.pcg_solve(h, 2, 4, src, x_ref, True)
+        torch.cuda.synchronize()
+        big = torch.randn(2048, 2048, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            bd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            for _ in range(6):
+                big = torch.tanh(big @ big / 2048.0)
+            bd.copy_(src)
+            z = torch.empty_like(bd)
+            amg.vcycle_apply(h, 2, 4, bd, z)
+            x = torch.empty_like(bd)
+            rc2, it2, _, _ = amg.pcg_solve(h, 2, 4, bd, x, True)
+        s.synchronize()
+        assert rc2 == rc == amg.AMG_OK and it2 == it_ref
+        assert torch.equal(z, z_ref) and torch.equal(x, x_ref)
+
+
+class _hier:
+    """Set up a handle on the default stream and destroy it at the end."""
+
+    def __init__(self, amg, A):
+        self.amg, self.A = amg, A
+
+    def __enter__(self):
+        self.h = _setup(self.amg, self.A.row_ptr, self.A.col, self.A.val, self.A.grid)
+        return self.h
+
+    def __exit__(self, *exc):
+        torch_cuda().cuda.synchronize()
+        self.amg.amg_destroy(self.h)
+        return False
