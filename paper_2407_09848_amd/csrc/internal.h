@@ -306,6 +306,8 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out);
 // box aggregates of edge e; children (2x2x2 boxes only) may be null
 int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int e, int32_t* agg, int32_t* children,
                       int* cnx, int* cny, int* cnz);
+// A_c = P^T A P for 2x2x2 boxes with unit prolongator entries (zero sums are kept); the three output
+// arrays belong to the caller from their allocation on, also when the call fails
 int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
              const int32_t* agg, int64_t nc, const int32_t* children, int32_t** cptr, int32_t** ccol,
              double** cval, int64_t* cnnz, int* flag);

@@ -512,8 +512,10 @@ int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, c
              const int32_t* agg, int64_t nc, const int32_t* children, int32_t** cptr, int32_t** ccol,
              double** cval, int64_t* cnnz, int* flag) {
   (void)n;
+  // the arrays belong to the caller as soon as they exist, also when a later step fails
   int32_t* cnt = nullptr;
   if (hipMalloc(&cnt, sizeof(int32_t) * (nc + 1)) != hipSuccess) return AMG_ENOMEM;
+  *cptr = cnt;
   hipLaunchKernelGGL((k_rap<false>), dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, s, nc, ptr, col, val, agg,
                      children, cnt, (int32_t*)nullptr, (double*)nullptr, flag);
   AMGP_HIP(hipGetLastError());
@@ -522,19 +524,13 @@ int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, c
   int hflag[F_NFLAG];
   AMGP_HIP(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, s));
   AMGP_HIP(hipStreamSynchronize(s));
-  if (hflag[F_CAPACITY]) {
-    hipFree(cnt);
-    return AMG_ECAPACITY;
-  }
+  if (hflag[F_CAPACITY]) return AMG_ECAPACITY;
   int64_t acc = 0;
   for (int64_t I = 0; I < nc; ++I) {
     const int32_t c = h[I];
     h[I] = (int32_t)acc;
     acc += c;
-    if (acc >= (int64_t)INT32_MAX) {
-      hipFree(cnt);
-      return AMG_ECAPACITY;
-    }
+    if (acc >= (int64_t)INT32_MAX) return AMG_ECAPACITY;
   }
   h[nc] = (int32_t)acc;
   AMGP_HIP(hipMemcpyAsync(cnt, h.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice, s));
@@ -544,7 +540,6 @@ int galerkin(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, c
                      children, cnt, *ccol, *cval, flag);
   AMGP_HIP(hipGetLastError());
   AMGP_HIP(hipStreamSynchronize(s));
-  *cptr = cnt;
   *cnnz = acc;
   return AMG_OK;
 }

@@ -705,8 +705,27 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     C.ny = cy;
     C.nz = cz;
     if (!L.general) {
-      AMGP_TRY(galerkin(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, L.agg, nc, L.children, &C.csr_ptr, &C.csr_col,
-                        &C.csr_val, &C.nnz, h->dflag));
+      int rc = galerkin(s, L.n, L.csr_ptr, L.csr_col, L.csr_val, L.agg, nc, L.children, &C.csr_ptr, &C.csr_col,
+                        &C.csr_val, &C.nnz, h->dflag);
+      // entries of the product that are exactly zero are not stored, as in a general sparse
+      // product: couplings carried only by zero stencil entries (the Q1 face entries between
+      // aggregates one cell wide in two directions)
+      Csr cc;
+      cc.m = nc;
+      cc.ncols = nc;
+      cc.nnz = C.nnz;
+      cc.ptr = C.csr_ptr;
+      cc.col = C.csr_col;
+      cc.val = C.csr_val;
+      if (rc == AMG_OK) rc = drop_small(s, &cc, 0.0);
+      C.csr_ptr = cc.ptr;
+      C.csr_col = cc.col;
+      C.csr_val = cc.val;
+      C.nnz = cc.nnz;
+      if (rc != AMG_OK) {
+        h->lv.push_back(C);  // owned by the handle from here on, also on error
+        return rc;
+      }
     } else {
       AMGP_TRY(general_level(h, s, L, &C, nullptr));
     }

@@ -98,11 +98,16 @@ def test_smoother_does_not_modify_b(amg):
 # ---------------------------------------------------------------------------
 # hierarchy: l1 diagonal, Galerkin operators, SpMV, transfers, coarse solve
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["poisson", "fv_odd", "q1", "batch"])
+@pytest.mark.parametrize("case", ["poisson", "fv_odd", "q1", "q1_11x6x7", "q1_10x7x7", "batch"])
 def test_hierarchy_matches_oracle(amg, case):
+    """The two Q1 grids of odd extents leave aggregates one cell wide in two directions on level 1,
+    coupled only through the stored zero face entries: the coarse patterns hold no such zeros."""
     torch = torch_cuda()
     nbatch = 1
-    if case == "poisson":
+    if case.startswith("q1_"):
+        A = W.q1_27pt(*[int(v) for v in case[3:].split("x")])
+        mc = 38 if case == "q1_11x6x7" else 14
+    elif case == "poisson":
         A = W.poisson3d_7pt(32)
         mc = 4096
     elif case == "fv_odd":
