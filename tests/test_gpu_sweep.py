@@ -5,7 +5,8 @@ threshold, Cholesky or swept coarsest level, polynomial kind and degree 1..12.
 Each seeded case checks, at the bars of the dedicated tests: the aggregate of every row, the
 level sizes and the Galerkin sparsity bit-exact, the coarse values within 1e-13 of the largest
 entry, two V-cycles within 1e-12, and the PCG iteration count exactly (a count one apart is accepted only when the oracle's residual
-at the stopping test lies within 1e-6 of the tolerance, the borderline reading of the stopping rule).
+at the stopping test lies within 1e-6 of the tolerance, the borderline reading of the stopping rule),
+with the residual history within 1e-6 relative or 1e-12 absolute.
 """
 import os
 import sys
@@ -121,5 +122,6 @@ def test_sweep_case_matches_oracle(amg, seed):
             lo = min(it, ro.iters)
             assert abs(it - ro.iters) == 1 and abs(ro.history[lo] / 1e-8 - 1.0) <= 1e-6, (tag, kind, k, it, ro.iters)
         else:
-            assert np.allclose(hist, ro.history, rtol=1e-6, atol=0), (tag, kind, k)
+            # relative residuals below 1e-12 are rounding noise (a one-level hierarchy solves exactly)
+            assert np.allclose(hist, ro.history, rtol=1e-6, atol=1e-12), (tag, kind, k)
             assert relerr(host(x), ro.x) <= 1e-9, (tag, kind, k)
