@@ -15,6 +15,9 @@ constexpr int kSlice = 64;    // sliced-ELL slice height = one wavefront, one ro
 constexpr int kBlock = 256;   // threads per block for row-parallel kernels (4 waves)
 constexpr int kMaxChildren = 8;  // 2x2x2 box aggregates
 constexpr int kDenseTile = 64;   // dense coarsest level padded to a multiple of this
+// coarse levels of 16..63 entries per row and at least this many rows take the offset-aligned
+// layout (one row per lane, no column indices) when their slices allow it
+constexpr int64_t kAlignedWideMinRows = int64_t(1) << 18;
 
 // Sliced ELLPACK matrix with G = `group` lanes per row (G in {1, 4, 16, 64}): a
 // slice holds 64 / G rows, one wavefront's worth.  Entry j of row r of slice s

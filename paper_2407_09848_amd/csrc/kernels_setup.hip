@@ -417,6 +417,12 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
     AMGP_HIP(hipStreamSynchronize(s));
     const double mean = (double)last / (double)n;
     group = mean >= 256 ? 64 : mean >= 64 ? 16 : mean >= 16 ? 4 : 1;
+    if (group == 4 && n >= kAlignedWideMinRows && ncols == n) {
+      // a coarse stencil (27 points on Q1 boxes) on a large level: one row per lane without
+      // column indices moves 4 bytes less per entry than four lanes per row with them
+      const int rc = build_ell_aligned(s, n, ptr, col, val, out);
+      if (rc != AMG_EINVAL) return rc;
+    }
   }
   if (group != 1 && group != 4 && group != 16 && group != 64) return AMG_EINVAL;
   if (group == 1 && ncols == n) {

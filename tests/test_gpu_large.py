@@ -106,6 +106,35 @@ def test_c5_smoother_sampled_rows(c5):
             _log(f"kind {kind}: {len(pts)} sampled rows match the oracle")
 
 
+def test_c5_coarse_stencil_level_aligned(c5):
+    """Level 1 of the 320^3 hierarchy (4.1M rows, a 27-point stencil) takes the offset-aligned
+    layout, one row per lane without column indices; the smoother on that level matches the
+    oracle's smoother on the level's exported CSR."""
+    torch = torch_cuda()
+    import scipy.sparse as sp
+    import paper_2407_09848_amd as amg
+    A, _, _ = c5
+    with hierarchy(A) as h:
+        padded, lanes, aligned = amg.amg_level_layout(h, 1)
+        n1, nnz1 = amg.amg_level_info(h, 1)[:2]
+        assert aligned and lanes == 1 and n1 == 160 ** 3, (padded, lanes, aligned, n1)
+        assert nnz1 <= padded <= 27 * n1
+        rp, cl, vl, _ = amg.amg_level_export(h, 1)
+        torch.cuda.synchronize()
+        Ac = sp.csr_matrix((host(vl), host(cl), host(rp)), shape=(n1, n1))
+        Minv = S.l1_diagonal(Ac)
+        r = np.random.default_rng(5).uniform(-1, 1, n1)
+        for kind in (2, 3):
+            x = nan_vec(n1)
+            amg.smoother_apply(h, 1, kind, 4, dev(r), x, True)
+            torch.cuda.synchronize()
+            beta, a = oracle_params(kind, 4)
+            xo = S.smooth(Ac, Minv, r, None, kind, 4, beta, a)
+            e = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+            _log(f"C5 level 1 ({padded} stored entries), kind {kind}: relative error {e:.2e}")
+            assert e <= 1e-12
+
+
 def test_c5_pcg_variants(c5):
     """AMG-PCG to 1e-8 on 320^3: plain FP64 optimal 4th kind, FP32 hierarchy, optimal 1st kind (k = 4);
     the true residual of each solution is checked with the oracle's SpMV."""
