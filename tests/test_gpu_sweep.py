@@ -23,7 +23,7 @@ from oracle import amg as OA  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-NCASES = 32
+NCASES = 160
 
 
 @pytest.fixture(scope="module")
