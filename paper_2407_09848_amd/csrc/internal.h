@@ -33,7 +33,10 @@ constexpr int64_t kAlignedWideMinRows = int64_t(1) << 18;
 // its rows (0 where a row has none), so the kernels form the column as
 // row + offset, clamped into [0, n), and read no column indices: 8 instead of
 // 12 bytes per stored FP64 entry.  `col` is still filled (with the same clamped
-// columns) for code that reads it.
+// columns) for code that reads it.  The FP32 copy of offset-aligned slices keeps
+// each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit at 128 q + 2 l and
+// 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so that one 8-byte
+// load per lane serves two steps; `col` keeps the unpaired order.
 template <typename T>
 struct Ell {
   int64_t n = 0;

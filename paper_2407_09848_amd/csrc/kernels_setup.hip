@@ -197,6 +197,22 @@ __global__ void k_round_f32(int64_t m, const double* __restrict__ a, float* __re
   if (i < m) b[i] = (float)a[i];
 }
 
+// FP32 copy of offset-aligned slices with each lane's steps in pairs: step t of lane l goes to
+// 64 (t - t % 2) + 2 l + t % 2 while t has a partner, an odd last step stays at 64 t + l.
+__global__ void k_round_f32_pairs(int64_t nslices, const int32_t* __restrict__ sptr, const double* __restrict__ a,
+                                  float* __restrict__ b) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = g >> 6;
+  const int lane = (int)(g & 63);
+  if (s >= nslices) return;
+  const int beg = sptr[s];
+  const int w = (sptr[s + 1] - beg) >> 6;
+  for (int t = 0; t < w; ++t) {
+    const int dst = t < (w & ~1) ? 64 * (t & ~1) + 2 * lane + (t & 1) : 64 * t + lane;
+    b[beg + dst] = (float)a[beg + 64 * t + lane];
+  }
+}
+
 // Box aggregates of edge e: row (i, j, k) of problem p -> coarse (i/e, j/e, k/e) of
 // problem p; an axis of extent 1 is not coarsened.  For e = 2, children[I*8 + c]
 // lists the rows of aggregate I in ascending order (z, then y, then x), -1 padded.
@@ -477,7 +493,12 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
     if (hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(e.padded / kSlice, 1)) != hipSuccess) return AMG_ENOMEM;
     AMGP_HIP(hipMemcpyAsync(e.doff, a.doff, sizeof(int32_t) * (e.padded / kSlice), hipMemcpyDeviceToDevice, s));
   }
-  hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
+  if (a.doff) {
+    hipLaunchKernelGGL(k_round_f32_pairs, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, e.nslices, e.sptr,
+                       a.val, e.val);
+  } else {
+    hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
+  }
   AMGP_HIP(hipGetLastError());
   *out = e;
   return AMG_OK;

@@ -73,6 +73,36 @@ __device__ __forceinline__ void st(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
+// FP32 offset-aligned slices keep each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit
+// at 128 q + 2 l and 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so one 8-byte
+// load per lane serves two steps and a wavefront load is 512 contiguous bytes, as in FP64.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ f32x2 ld2(const float* p) {
+  const f32x2* q = reinterpret_cast<const f32x2*>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q); else return *q;
+}
+
+// Sum over the steps t of an FP32 offset-aligned slice [beg, end) of val_t * g(column_t), in
+// ascending t (the order of the FP64 loops), for the row r served by this lane.
+template <bool NT, typename Gf>
+__device__ __forceinline__ float aligned_sum_f32(const float* __restrict__ val, int beg, int end, int lane,
+                                                 const int32_t* __restrict__ off, int r, int last, Gf g) {
+  const int w = (end - beg) >> 6;
+  const float* v = val + beg;
+  float acc = 0.0f;
+  int t = 0;
+  for (; t + 1 < w; t += 2) {
+    const f32x2 p = ld2<NT>(v + 64 * t + 2 * lane);
+    const int c0 = min(max(r + off[t], 0), last);
+    const int c1 = min(max(r + off[t + 1], 0), last);
+    acc += p.x * g(c0);
+    acc += p.y * g(c1);
+  }
+  if (t < w) acc += ld<NT>(v + 64 * t + lane) * g(min(max(r + off[t], 0), last));
+  return acc;
+}
+
 // Rows with G lanes each (Ell::group): thread t of the grid serves row t / G, and a
 // wavefront covers exactly one slice of 64 / G rows.
 template <int G>
@@ -103,6 +133,9 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
     // offset-aligned slice: the column is the row plus the step's (uniform) offset
     const int32_t* off = A.doff + (beg >> 6);
     const int r = (int)row;
+    if constexpr (std::is_same_v<T, float>) {
+      return aligned_sum_f32<NT>(A.val, beg, end, lane, off, r, A.last, [&](int c) { return x[c]; });
+    }
 #pragma unroll 2
     for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(r + off[t], 0), A.last);
@@ -252,11 +285,17 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   T ag = T(0);
   if (G == 1 && A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
+    if constexpr (std::is_same_v<T, float>) {
+      ag = aligned_sum_f32<NT>(A.val, beg, end, lane, off, (int)i, A.last, [&](int j) {
+        return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
+      });
+    } else {
 #pragma unroll 2
-    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
-      const int j = min(max((int)i + off[t], 0), A.last);
-      const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-      ag += ld<NT>(A.val + p) * g1j;
+      for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
+        const int j = min(max((int)i + off[t], 0), A.last);
+        const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
+        ag += ld<NT>(A.val + p) * g1j;
+      }
     }
   } else {
 #pragma unroll 4
@@ -328,6 +367,10 @@ __device__ __forceinline__ T ell_dot_prol(EllView<T> A, int64_t row, const T* __
   if (A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
     const int r = (int)row;
+    if constexpr (std::is_same_v<T, float>) {
+      return aligned_sum_f32<NT>(A.val, beg, end, lane, off, r, A.last,
+                                 [&](int c) { return x[c] + pr.xc[pr.agg[c]]; });
+    }
 #pragma unroll 2
     for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(r + off[t], 0), A.last);
@@ -413,6 +456,9 @@ __device__ __forceinline__ T ell_dot_any(EllView<T> A, int row, const T* __restr
   T acc = T(0);
   if (A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
+    if constexpr (std::is_same_v<T, float>) {
+      return aligned_sum_f32<NT>(A.val, beg, end, row & 63, off, row, A.last, [&](int c) { return x[c]; });
+    }
 #pragma unroll 2
     for (int p = beg + (row & 63), t = 0; p < end; p += kSlice, ++t) {
       const int c = min(max(row + off[t], 0), A.last);
