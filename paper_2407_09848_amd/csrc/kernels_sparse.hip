@@ -92,6 +92,7 @@ __device__ __forceinline__ float aligned_sum_f32(const float* __restrict__ val, 
   const float* v = val + beg;
   float acc = 0.0f;
   int t = 0;
+#pragma unroll 2
   for (; t + 1 < w; t += 2) {
     const f32x2 p = ld2<NT>(v + 64 * t + 2 * lane);
     const int c0 = min(max(r + off[t], 0), last);
