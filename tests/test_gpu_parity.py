@@ -262,6 +262,29 @@ def test_fp32_hierarchy(amg):
             assert relerr(xr, ro.x) <= 1e-6
 
 
+@pytest.mark.parametrize("case", ["q1_20", "fv_ragged"])
+def test_fp32_aligned_smoother(amg, case):
+    """FP32 smoother on offset-aligned fine levels, whose float values sit in step pairs with an odd
+    last step (27 and 7 offsets inside, fewer in boundary slices): every kind at degrees 1..6 stays
+    within FP32 rounding of the FP64 oracle smoother (parity unpinned: no exact FP32 answer)."""
+    torch = torch_cuda()
+    A = W.q1_27pt(20) if case == "q1_20" else _fv((13, 11, 9), 1.0, 6)
+    As = A.to_scipy()
+    Minv = S.l1_diagonal(As)
+    r = np.random.default_rng(21).uniform(-1, 1, A.n)
+    with hierarchy(A, precision=amg.AMG_FP32) as h:
+        _, lanes, aligned = amg.amg_level_layout(h, 0)
+        assert aligned and lanes == 1
+        for kind in KINDS:
+            for k in range(1, 7):
+                x = nan_vec(A.n)
+                amg.smoother_apply(h, 0, kind, k, dev(r), x, True)
+                torch.cuda.synchronize()
+                beta, a = oracle_params(kind, k)
+                e = relerr(host(x), S.smooth(As, Minv, r, None, kind, k, beta, a))
+                assert e <= 1e-5, (case, kind, k, e)
+
+
 def test_vcycle_full_size_c2(amg):
     """128^3 7-point Poisson, optimal 4th kind k = 4: the whole V-cycle output vs the oracle."""
     torch = torch_cuda()
