@@ -196,9 +196,12 @@ __global__ __launch_bounds__(TM) void k_symv_tiles(int nb, int ntiles, int64_t n
   const double bJ = rj < nl ? (double)bp[rj] : 0.0;
   const double* src = packed + ((int64_t)p * ntiles + q) * TM * TM + lane;
   double col = 0.0;
+  // the tiles (67 MB at 4096 rows) are read once per cycle with streaming loads, so that they do
+  // not displace the fine level's matrix and vectors from the caches (measured at 128^3: 18.3 to
+  // 16.2 us here, and the whole PCG solve 9.20 to 9.00 ms)
 #pragma unroll 16
   for (int a = 0; a < TM; ++a) {
-    const double v = src[a * TM];
+    const double v = __builtin_nontemporal_load(src + a * TM);
     col += v * __shfl(bJ, a, TM);
     prod[a][lane] = v * bI;
   }
