@@ -585,6 +585,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
                                                        const TZ* __restrict__ z, const double* __restrict__ pold,
                                                        double* __restrict__ pnew, double* __restrict__ q,
                                                        double* __restrict__ partial) {
+  // with an FP32 hierarchy (float z) this product is the only reader of the FP64 matrix, once
+  // per iteration: its values are streamed so that they do not displace the FP32 smoother's
+  // matrix and vectors from the caches (128^3: FP32-hierarchy solve 6.63 to 6.36 ms)
+  constexpr bool kStreamVal = NT || std::is_same_v<TZ, float>;
   const int64_t i = row_index();
   const double beta = scal[S_BETA];
   double v = 0.0;
@@ -598,13 +602,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
 #pragma unroll 2
       for (int p = beg + (int)(i & 63), t = 0; p < end; p += kSlice, ++t) {
         const int j = min(max((int)i + off[t], 0), A.last);
-        acc += ld<NT>(A.val + p) * ((double)z[j] + beta * pold[j]);
+        acc += ld<kStreamVal>(A.val + p) * ((double)z[j] + beta * pold[j]);
       }
     } else {
 #pragma unroll 4
       for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
         const int j = ld<NT>(A.col + p);
-        acc += ld<NT>(A.val + p) * ((double)z[j] + beta * pold[j]);
+        acc += ld<kStreamVal>(A.val + p) * ((double)z[j] + beta * pold[j]);
       }
     }
     const double pi = z[i] + beta * pold[i];
