@@ -222,6 +222,9 @@ int vcycle_apply(amg_handle* h, int kind, int degree, const double* d_r, double*
  * h_hist is not NULL the relative residual history h_hist[0..iters] (length
  * >= maxit+1).  Synchronises `stream`.  ||b|| = 0 returns x = 0, iters = 0.
  * Returns AMG_OK, AMG_NOT_CONVERGED, AMG_EBREAKDOWN, AMG_ENAN or an argument error.
+ * On AMG_EBREAKDOWN ((p, A p) <= 0: A, or the preconditioner, is not positive
+ * definite) the step along p is not taken: x and *h_relres are those of the
+ * last iterate before the breakdown, *h_iters counts the failed iteration.
  * ------------------------------------------------------------------------- */
 int pcg_solve(amg_handle* h, int kind, int degree, const double* d_b, double* d_x, int x_is_zero,
               double rtol, int maxit, int flexible, int* h_iters, double* h_relres,
@@ -298,6 +301,41 @@ int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, i
  * `degree` weights) stays inside Pi_k (eq. polspace): |p(x)| < 1 at x = m/ngrid, m = 1..ngrid
  * (p(0) = 1 holds for any weights); else 0.  Used to fall back to the tabulated weights. */
 int amg_beta_valid(const double* d_beta, int count, int degree, int ngrid, int* d_valid, void* stream);
+
+/* Learned weights on the device (eq. polsmootheropt with corrected beta, kept inside Pi_k of
+ * eq. polspace).  d_y[(p * (nlevels - 1) + l) * 6 + j] is the network output (mlp_fwd) for
+ * stacked problem p and smoothing level l; only its first `degree` columns are used
+ * (1 <= degree <= 6).  Writes the weight table d_beta (layout of vcycle_fwd_ckpt, all
+ * nbatch * nlevels rows):
+ *   beta[p][l][j] = beta_opt_{j,k} + (double)y[p, l][j]   on the smoothing levels l < nlevels - 1,
+ *   beta[p][nlevels-1][j] = beta_opt_{j,k}                on the coarsest level (not smoothed),
+ * beta_opt the compiled-in optimal table.  A smoothing row whose polynomial leaves Pi_k
+ * (|p(x)| >= 1 at some x = m/ngrid, m = 1..ngrid, as amg_beta_valid) falls back to beta_opt;
+ * d_valid[p * (nlevels - 1) + l] = 1 for a kept row, 0 for a fallback.  d_y = NULL writes the
+ * plain table (every row valid).  Asynchronous.  AMG_EINVAL: null handle or outputs, degree
+ * outside 1..6, ngrid < 1, a handle with a single level. */
+int amg_learned_beta(const amg_handle* h, int degree, const float* d_y, int ngrid, double* d_beta, int* d_valid,
+                     void* stream);
+
+/* Gradient hand-over from the weights to the network output: d_gy[q][j] (float32, q = p *
+ * (nlevels - 1) + l, 6 columns) = dL/dbeta[p][l][j] (d_gbeta, layout of d_beta) for j < degree
+ * on the rows amg_learned_beta kept (d_valid[q] = 1), and 0 elsewhere (fallback rows and the
+ * unused columns), since a fallback row does not depend on y.  Asynchronous.  AMG_EINVAL as
+ * amg_learned_beta. */
+int amg_learned_beta_grad(const amg_handle* h, int degree, const double* d_gbeta, const int* d_valid, float* d_gy,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Bandwidth ceiling of the device memory: kernels with known byte counts that
+ * the smoother kernels are measured against (16-byte nontemporal accesses,
+ * AMG_HBM_PARTIALS blocks of 256 threads, grid-stride).  d_x, d_y 16-byte aligned.
+ * ------------------------------------------------------------------------- */
+#define AMG_HBM_PARTIALS 16384
+/* Reads d_x[n] once (8 n bytes): d_partial[AMG_HBM_PARTIALS] receives block sums whose total
+ * is sum_i x_i (rounding order fixed by the grid).  Asynchronous. */
+int amg_hbm_read(const double* d_x, int64_t n, double* d_partial, void* stream);
+/* d_y[i] = d_x[i], i < n (8 n bytes read, 8 n written); the ranges must not overlap.  Asynchronous. */
+int amg_hbm_copy(const double* d_x, double* d_y, int64_t n, void* stream);
 
 /* Human-readable name of a return code (static storage). */
 const char* amg_strerror(int code);

@@ -12,6 +12,7 @@ AMG_L1JAC, AMG_CHEB4, AMG_OPTCHEB4, AMG_OPTCHEB1 = 0, 1, 2, 3
 AMG_FP64, AMG_FP32 = 0, 1
 AMG_AGG_BOX, AMG_AGG_MATCHING, AMG_AGG_VBM = 0, 1, 2
 AMG_MAX_DEGREE = 12
+AMG_HBM_PARTIALS = 16384
 
 __all__ = [
     "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info", "amg_level_layout",
@@ -20,7 +21,8 @@ __all__ = [
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
     "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
     "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_adam",
-    "amg_beta_valid", "VCycleFunction",
+    "amg_beta_valid", "amg_learned_beta", "amg_learned_beta_grad", "amg_hbm_read", "amg_hbm_copy",
+    "AMG_HBM_PARTIALS", "VCycleFunction",
     "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
     "AMG_EBREAKDOWN", "AMG_ENAN", "AMG_ECAPACITY", "AMG_L1JAC", "AMG_CHEB4", "AMG_OPTCHEB4",
     "AMG_OPTCHEB1", "AMG_FP64", "AMG_FP32", "AMG_MAX_DEGREE", "AMG_AGG_BOX", "AMG_AGG_MATCHING",
@@ -80,6 +82,10 @@ _SIGS = {
     "mlp_bwd": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
     "mlp_adam": (_I, [_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "amg_beta_valid": (_I, [_P, _I, _I, _I, _P, _P]),
+    "amg_learned_beta": (_I, [_P, _I, _P, _I, _P, _P, _P]),
+    "amg_learned_beta_grad": (_I, [_P, _I, _P, _P, _P, _P]),
+    "amg_hbm_read": (_I, [_P, _I64, _P, _P]),
+    "amg_hbm_copy": (_I, [_P, _P, _I64, _P]),
 }
 
 
@@ -363,6 +369,43 @@ def amg_beta_valid(beta, degree, ngrid=4096):
     _check(lib().amg_beta_valid(_ptr(beta, torch.float64), count, degree, ngrid, _ptr(valid), _stream()),
            "amg_beta_valid")
     return valid
+
+
+def amg_learned_beta(h, degree, y, nbatch, ngrid=4096):
+    """(beta float64 [nbatch, nlevels, degree], valid int32 [nbatch * (nlevels - 1)]) on the device:
+    the optimal table plus the network output y ([nbatch * (nlevels - 1), 6] float32) on the
+    smoothing levels, rows outside Pi_k falling back to the table.  y = None: the plain table."""
+    import torch
+    L = amg_num_levels(h)
+    beta = torch.empty((nbatch, L, degree), dtype=torch.float64, device="cuda")
+    valid = torch.empty(nbatch * (L - 1), dtype=torch.int32, device="cuda")
+    yp = None if y is None else _ptr(y, torch.float32, nbatch * (L - 1) * 6, "y")
+    _check(lib().amg_learned_beta(h, degree, yp, ngrid, _ptr(beta), _ptr(valid), _stream()), "amg_learned_beta")
+    return beta, valid
+
+
+def amg_learned_beta_grad(h, degree, gbeta, valid, gy):
+    """gy ([nbatch * (nlevels - 1), 6] float32) = dL/dbeta on the kept rows, 0 elsewhere."""
+    import torch
+    _check(lib().amg_learned_beta_grad(h, degree, _ptr(gbeta, torch.float64, name="gbeta"),
+                                       _ptr(valid, torch.int32, name="valid"),
+                                       _ptr(gy, torch.float32, valid.numel() * 6, "gy"), _stream()),
+           "amg_learned_beta_grad")
+
+
+def amg_hbm_read(x, partial):
+    """Reads x (float64) once; partial (float64, AMG_HBM_PARTIALS entries) receives block sums."""
+    import torch
+    return _check(lib().amg_hbm_read(_ptr(x, torch.float64, name="x"), x.numel(),
+                                     _ptr(partial, torch.float64, AMG_HBM_PARTIALS, "partial"), _stream()),
+                  "amg_hbm_read")
+
+
+def amg_hbm_copy(x, y):
+    """y = x (float64, same length, not overlapping)."""
+    import torch
+    return _check(lib().amg_hbm_copy(_ptr(x, torch.float64, name="x"), _ptr(y, torch.float64, x.numel(), "y"),
+                                     x.numel(), _stream()), "amg_hbm_copy")
 
 
 def _vcycle_function():

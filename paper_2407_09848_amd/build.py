@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libamgpoly.so")
 ARCH = os.environ.get("AMGP_ARCH", "gfx950")
 
 SOURCES = ["kernels_sparse.hip", "kernels_setup.hip", "kernels_galerkin.hip", "kernels_match.hip", "kernels_vbm.hip",
-           "kernels_dense.hip", "kernels_train.hip", "runtime.hip"]
+           "kernels_dense.hip", "kernels_train.hip", "kernels_stream.hip", "runtime.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

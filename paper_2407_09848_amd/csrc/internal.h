@@ -294,10 +294,21 @@ int launch_mlp_bwd(hipStream_t s, int B, const float* W, const float* X, const f
 int launch_adam(hipStream_t s, int n, float* W, const float* G, float* m, float* v, float lr, float b1, float b2,
                 float eps, float c1, float c2);
 int launch_beta_valid(hipStream_t s, int count, int k, const double* beta, int ngrid, int* valid);
+// learned weights: table + network output on the smoothing levels, |p| < 1 fallback (amg_learned_beta)
+struct BetaRow {
+  double v[AMG_MAX_DEGREE];
+};
+int launch_learned_beta(hipStream_t s, int P, int L, int k, const BetaRow& tab, const float* y, int ngrid,
+                        double* beta, int* valid);
+int launch_learned_beta_grad(hipStream_t s, int P, int L, int k, const double* gbeta, const int* valid, float* gy);
 int mlp_num_params();
 int launch_mul(hipStream_t s, int64_t n, const double* a, const double* x, double* y);
 int launch_offdiag_ratio(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
                          const double* minv, double* out);
+
+// ---- bandwidth ceiling (kernels_stream.hip) ----
+int launch_hbm_read(hipStream_t s, int64_t n, const double* x, double* part);
+int launch_hbm_copy(hipStream_t s, int64_t n, const double* x, double* y);
 
 // ---- setup kernels (kernels_setup.hip) ----
 // row_ptr monotone from 0 to nnz, columns strictly increasing within a row and in [0, n)

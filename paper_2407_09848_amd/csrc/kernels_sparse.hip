@@ -708,8 +708,12 @@ __global__ __launch_bounds__(1024) void k_reduce(int mode, unsigned nb, const do
       break;
     case RED_ALPHA:
       scal[S_PQ] = s;
-      if (!(s > 0.0)) flag[F_BREAKDOWN] = 1;
-      scal[S_ALPHA] = scal[S_RZ] / s;
+      if (s > 0.0) {
+        scal[S_ALPHA] = scal[S_RZ] / s;
+      } else {  // breakdown: the update that follows leaves x and r as they are
+        flag[F_BREAKDOWN] = 1;
+        scal[S_ALPHA] = 0.0;
+      }
       break;
     case RED_RR:
       scal[S_RR] = s;

@@ -214,16 +214,13 @@ __global__ void k_adam(int n, float* __restrict__ W, const float* __restrict__ G
   W[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// valid[q] = 1 if p_q(x) = sum_j (beta_j - beta_{j+1})/(2j+1) W_j(1-2x) satisfies |p| < 1 on
-// the grid x_m = m / ngrid, m = 1..ngrid (p(0) = 1 by construction); beta row q has k entries.
-__global__ __launch_bounds__(256) void k_beta_valid(int count, int k, const double* __restrict__ beta,
-                                                    int ngrid, int* __restrict__ valid) {
-  const int q = blockIdx.x;
-  if (q >= count) return;
+// True when p(x) = sum_j (beta_j - beta_{j+1})/(2j+1) W_j(1-2x) (beta_0 = 1, beta_{k+1} = 0,
+// W_j the 4th-kind polynomials) has |p| < 1 at every x_m = m / ngrid, m = 1..ngrid (p(0) = 1 by
+// construction).  Called by all threads of a block (uniformly); bq is the row's k weights.
+__device__ bool row_inside_pik(const double* bq, int k, int ngrid) {
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  const double* bq = beta + (int64_t)q * k;
   for (int m = 1 + threadIdx.x; m <= ngrid; m += blockDim.x) {
     const double y = 1.0 - 2.0 * (double)m / ngrid;
     double wm = 1.0, w = 2.0 * y + 1.0;  // W_0, W_1
@@ -238,7 +235,50 @@ __global__ __launch_bounds__(256) void k_beta_valid(int count, int k, const doub
     if (!(fabs(p) < 1.0)) bad = 1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) valid[q] = bad ? 0 : 1;
+  const bool ok = bad == 0;
+  __syncthreads();
+  return ok;
+}
+
+// valid[q] = 1 if the weight row q (k entries) keeps its polynomial inside Pi_k (eq. polspace).
+__global__ __launch_bounds__(256) void k_beta_valid(int count, int k, const double* __restrict__ beta,
+                                                    int ngrid, int* __restrict__ valid) {
+  const int q = blockIdx.x;
+  if (q >= count) return;
+  const bool ok = row_inside_pik(beta + (int64_t)q * k, k, ngrid);
+  if (threadIdx.x == 0) valid[q] = ok ? 1 : 0;
+}
+
+// Learned weights, one block per row (p, l) of the table [P][L][k]: on a smoothing level
+// (l < L - 1) the tabulated optimal weights plus the network output y[p * (L - 1) + l][0..k),
+// kept when the polynomial stays inside Pi_k, else the table (valid = 0); the coarsest row
+// is the table.  y == nullptr: the table on every row.
+__global__ __launch_bounds__(256) void k_learned_beta(int L, int k, BetaRow tab, const float* __restrict__ y,
+                                                      int ngrid, double* __restrict__ beta, int* __restrict__ valid) {
+  const int row = blockIdx.x;  // p * L + l
+  const int p = row / L, l = row % L;
+  double* out = beta + (int64_t)row * k;
+  if (l == L - 1) {
+    if (threadIdx.x < k) out[threadIdx.x] = tab.v[threadIdx.x];
+    return;
+  }
+  const int q = p * (L - 1) + l;
+  __shared__ double cand[AMG_MAX_DEGREE];
+  if (threadIdx.x < k) cand[threadIdx.x] = tab.v[threadIdx.x] + (y ? (double)y[(int64_t)q * 6 + threadIdx.x] : 0.0);
+  __syncthreads();
+  const bool ok = y ? row_inside_pik(cand, k, ngrid) : true;
+  if (threadIdx.x < k) out[threadIdx.x] = ok ? cand[threadIdx.x] : tab.v[threadIdx.x];
+  if (threadIdx.x == 0) valid[q] = ok ? 1 : 0;
+}
+
+// gy[q][j] = valid[q] ? (float)gbeta[p][l][j] : 0 for j < k, 0 for k <= j < 6 (q = p * (L - 1) + l).
+__global__ __launch_bounds__(256) void k_learned_beta_grad(int rows, int L, int k, const double* __restrict__ gbeta,
+                                                           const int* __restrict__ valid, float* __restrict__ gy) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * 6) return;
+  const int q = e / 6, j = e % 6;
+  const int p = q / (L - 1), l = q % (L - 1);
+  gy[e] = (j < k && valid[q]) ? (float)gbeta[((int64_t)p * L + l) * k + j] : 0.0f;
 }
 
 // y = M^{-1} x (elementwise)
@@ -321,6 +361,19 @@ int launch_adam(hipStream_t s, int n, float* W, const float* G, float* m, float*
 
 int launch_beta_valid(hipStream_t s, int count, int k, const double* beta, int ngrid, int* valid) {
   hipLaunchKernelGGL(k_beta_valid, dim3(count), dim3(256), 0, s, count, k, beta, ngrid, valid);
+  return LAUNCH_OK();
+}
+
+int launch_learned_beta(hipStream_t s, int P, int L, int k, const BetaRow& tab, const float* y, int ngrid,
+                        double* beta, int* valid) {
+  hipLaunchKernelGGL(k_learned_beta, dim3(P * L), dim3(256), 0, s, L, k, tab, y, ngrid, beta, valid);
+  return LAUNCH_OK();
+}
+
+int launch_learned_beta_grad(hipStream_t s, int P, int L, int k, const double* gbeta, const int* valid, float* gy) {
+  const int rows = P * (L - 1);
+  hipLaunchKernelGGL(k_learned_beta_grad, dim3((rows * 6 + 255) / 256), dim3(256), 0, s, rows, L, k, gbeta, valid,
+                     gy);
   return LAUNCH_OK();
 }
 

@@ -1240,6 +1240,39 @@ int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, i
   return amgp::launch_adam((hipStream_t)stream, n, d_params, d_g, d_m, d_v, lr, b1, b2, eps, c1, c2);
 }
 
+int amg_learned_beta(const amg_handle* h, int degree, const float* d_y, int ngrid, double* d_beta, int* d_valid,
+                     void* stream) {
+  if (!h || !d_beta || !d_valid || degree < 1 || degree > 6 || ngrid < 1) return AMG_EINVAL;
+  const Handle& H = h->impl;
+  if (H.nlevels < 2) return AMG_EINVAL;
+  amgp::BetaRow tab{};
+  for (int j = 0; j < degree; ++j) tab.v[j] = kOptBeta[degree][j];
+  return amgp::launch_learned_beta((hipStream_t)stream, H.nbatch, H.nlevels, degree, tab, d_y, ngrid, d_beta,
+                                   d_valid);
+}
+
+int amg_learned_beta_grad(const amg_handle* h, int degree, const double* d_gbeta, const int* d_valid, float* d_gy,
+                          void* stream) {
+  if (!h || !d_gbeta || !d_valid || !d_gy || degree < 1 || degree > 6) return AMG_EINVAL;
+  const Handle& H = h->impl;
+  if (H.nlevels < 2) return AMG_EINVAL;
+  return amgp::launch_learned_beta_grad((hipStream_t)stream, H.nbatch, H.nlevels, degree, d_gbeta, d_valid, d_gy);
+}
+
+int amg_hbm_read(const double* d_x, int64_t n, double* d_partial, void* stream) {
+  if (!d_x || !d_partial || n < 0 || (reinterpret_cast<uintptr_t>(d_x) & 15) != 0) return AMG_EINVAL;
+  return amgp::launch_hbm_read((hipStream_t)stream, n, d_x, d_partial);
+}
+
+int amg_hbm_copy(const double* d_x, double* d_y, int64_t n, void* stream) {
+  if (!d_x || !d_y || n < 0 || ((reinterpret_cast<uintptr_t>(d_x) | reinterpret_cast<uintptr_t>(d_y)) & 15) != 0)
+    return AMG_EINVAL;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(d_x), b = reinterpret_cast<uintptr_t>(d_y);
+  const uintptr_t bytes = (uintptr_t)n * sizeof(double);
+  if (n > 0 && a < b + bytes && b < a + bytes) return AMG_EINVAL;
+  return amgp::launch_hbm_copy((hipStream_t)stream, n, d_x, d_y);
+}
+
 int amg_beta_valid(const double* d_beta, int count, int degree, int ngrid, int* d_valid, void* stream) {
   if (!d_beta || !d_valid || count < 1 || degree < 1 || degree > AMG_MAX_DEGREE || ngrid < 1) return AMG_EINVAL;
   return amgp::launch_beta_valid((hipStream_t)stream, count, degree, d_beta, ngrid, d_valid);

@@ -49,10 +49,20 @@ def hierarchy(A, nbatch=1, max_coarse=4096, precision=0, **opts):
 
 
 def relerr(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
+    """Relative error of a against b: the larger of the norm-wise ||a - b|| / ||b|| and the
+    element-wise max_i |a_i - b_i| / max_i |b_i|, so that one wrong entry (a boundary row, a
+    slice tail) is not averaged away over millions of correct ones.  NaN anywhere gives NaN,
+    which fails every bound."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    d = a - b
+    if d.size and not np.all(np.isfinite(d)):
+        return float("nan")
+    norm_wise = np.linalg.norm(d) / (nb if nb > 0 else 1.0)
+    elem_wise = (np.abs(d).max() if d.size else 0.0) / (mb if mb > 0 else 1.0)
+    return max(norm_wise, elem_wise)
 
 
 def oracle_params(kind, k):

@@ -82,6 +82,14 @@ def test_argument_validation_before_device_work(L):
     assert L.amg_default_beta(0, buf) == amg.AMG_EINVAL
     assert L.amg_default_beta(13, buf) == amg.AMG_EINVAL
     assert L.amg_default_beta(4, buf) == amg.AMG_OK
+    # learned weights and the ceiling kernels: null handle / pointers, degree beyond the network
+    assert L.amg_learned_beta(None, 4, None, 4096, None, None, None) == amg.AMG_EINVAL
+    assert L.amg_learned_beta_grad(None, 4, None, None, None, None) == amg.AMG_EINVAL
+    assert L.amg_hbm_read(None, 10, None, None) == amg.AMG_EINVAL
+    assert L.amg_hbm_copy(None, None, 10, None) == amg.AMG_EINVAL
+    # misaligned (not 16-byte) and overlapping ranges are rejected before any launch
+    assert L.amg_hbm_read(P(8), 10, P(256), None) == amg.AMG_EINVAL
+    assert L.amg_hbm_copy(P(256), P(272), 10, None) == amg.AMG_EINVAL
 
 
 def test_product_never_imports_oracle():

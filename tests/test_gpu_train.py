@@ -101,6 +101,79 @@ def test_train_loss_grad_matches_oracle(amg):
     assert np.allclose(gh[:, :L - 1], go, rtol=1e-9, atol=1e-12 * np.abs(go).max())
 
 
+def test_train_loss_grad_degree6_matches_oracle(amg):
+    """FP64 at the learned-weights degree (k = 6) on a stack with that workload's three-level
+    structure (fine, one box level, dense coarsest): loss and every gradient entry against the
+    complex-step oracle."""
+    torch = torch_cuda()
+    k, P_, n = 6, 3, 16
+    mats, big = _stack(n, P_, seed0=75)
+    Hs = [OA.build_hierarchy(m.to_scipy(), m.grid, max_coarse=64) for m in mats]
+    assert len(Hs[0].levels) == 3
+    b = W.rhs_uniform(big.n, 9)
+    m0 = mats[0].n
+    bs = [b[p * m0:(p + 1) * m0] for p in range(P_)]
+    with hierarchy(big, nbatch=P_, max_coarse=64) as h:
+        L = amg.amg_num_levels(h)
+        assert L == 3
+        tab = _beta_table(k, P_, L, 13)
+        beta = dev(tab.ravel())
+        g = torch.empty_like(beta)
+        loss, ratios = amg.amg_train_loss_grad(h, k, beta, dev(b), g, P_)
+        torch.cuda.synchronize()
+        gh = host(g).reshape(P_, L, k)
+    betas = [[tab[p, l] for l in range(L - 1)] for p in range(P_)]
+    for p in range(P_):
+        assert ratios[p] == pytest.approx(AD.two_cycle_ratio(Hs[p], bs[p], k, betas[p]), rel=1e-12)
+    assert loss == pytest.approx(AD.loss(Hs, bs, k, betas), rel=1e-12)
+    go = AD.grad_complex_step(Hs, bs, k, betas)
+    assert np.allclose(gh[:, :L - 1], go, rtol=1e-9, atol=1e-12 * np.abs(go).max())
+    assert np.all(gh[:, L - 1] == 0)
+
+
+def test_learned_beta_composition_and_gradient_handover(amg):
+    """amg_learned_beta: table + network output on the smoothing rows, the plain table on the
+    coarsest row, fallback to the table where the polynomial leaves Pi_k (the oracle's polynomial
+    on the same grid decides); amg_learned_beta_grad: dL/dbeta on the kept rows, zero elsewhere."""
+    torch = torch_cuda()
+    k, P_, n = 6, 4, 12
+    mats, big = _stack(n, P_, seed0=140)
+    base = np.array(P.optimal_beta(k)[0])
+    xs = np.arange(1, 4097) / 4096.0
+    with hierarchy(big, nbatch=P_, max_coarse=27) as h:
+        L = amg.amg_num_levels(h)
+        rows = P_ * (L - 1)
+        scales = [1.0, 0.9, 1.05, 1.3, 1.6, 2.0, 0.97, 1.1]
+        y = np.zeros((rows, 6), dtype=np.float32)
+        rng = np.random.default_rng(21)
+        for q in range(rows):
+            y[q, :k] = (base * (scales[q % len(scales)] - 1.0) + 1e-3 * rng.standard_normal(k)).astype(np.float32)
+        beta, valid = amg.amg_learned_beta(h, k, dev(y), P_)
+        plain, pvalid = amg.amg_learned_beta(h, k, None, P_)
+        gb = rng.standard_normal((P_, L, k))
+        gy = torch.full((rows, 6), float("nan"), dtype=torch.float32, device="cuda")
+        amg.amg_learned_beta_grad(h, k, dev(gb.ravel()), valid, gy)
+        torch.cuda.synchronize()
+        bh, vh, ph, pvh, gyh = host(beta), host(valid), host(plain), host(pvalid), host(gy)
+    assert np.all(pvh == 1) and np.all(ph == np.tile(base, (P_, L, 1)))
+    expect_valid = []
+    for p in range(P_):
+        for l in range(L):
+            if l == L - 1:
+                assert np.all(bh[p, l] == base)
+                continue
+            q = p * (L - 1) + l
+            cand = base + y[q, :k].astype(np.float64)
+            ok = int(np.abs(P.p_optcheb4(cand, xs)).max() < 1.0)
+            expect_valid.append(ok)
+            assert np.all(bh[p, l] == (cand if ok else base)), (p, l)
+    assert list(vh) == expect_valid and 0 in expect_valid and 1 in expect_valid
+    for q in range(rows):
+        p, l = divmod(q, L - 1)
+        want = gb[p, l].astype(np.float32) if vh[q] else np.zeros(k, dtype=np.float32)
+        assert np.all(gyh[q, :k] == want) and np.all(gyh[q, k:] == 0), q
+
+
 def test_train_loss_grad_fp32(amg):
     """FP32 hierarchy: loss and gradient within FP32 rounding of the FP64 oracle (parity unpinned for FP32)."""
     torch = torch_cuda()
@@ -227,8 +300,8 @@ def test_level_features(amg):
 
 def test_learned_beta_gains_over_plain(amg):
     """Train the network (FP32, hand-written kernels) on stacked diffusion problems; the learned weights
-    must lower the two-cycle residual ratio on the training problems, and on held-out problems the
-    learned-with-fallback weights are never worse than the plain optimal weights."""
+    must lower the two-cycle residual ratio on the training problems and, by at least 5%, on
+    held-out problems of the same family (other random fields and right-hand side)."""
     torch = torch_cuda()
     from paper_2407_09848_amd import learned
     k, P_, n = 6, 6, 24
@@ -249,10 +322,10 @@ def test_learned_beta_gains_over_plain(amg):
     with hierarchy(big2, nbatch=P_, max_coarse=512, precision=amg.AMG_FP32) as h2:
         feats2 = amg.amg_level_features(h2, k, sig)
         beta2, _, _ = learned.predict_beta(h2, res.params, feats2, k, P_)
-        L2 = amg.amg_num_levels(h2)
-        plain = dev(np.tile(np.array(amg.amg_default_beta(k)), (P_, L2, 1)).ravel())
+        plain = learned.plain_beta(h2, k, P_)
         l_learned, _ = learned.evaluate(h2, beta2, dev(b2), k, P_)
         l_plain, _ = learned.evaluate(h2, plain, dev(b2), k, P_)
-    final = min(l_learned, l_plain)  # the plain weights are the fallback and the yardstick
-    print(f"held out: plain {l_plain:.6f} learned {l_learned:.6f} gain {100 * (1 - l_learned / l_plain):.2f}%")
-    assert final <= l_plain
+    gain = 1 - l_learned / l_plain
+    print(f"held out: plain {l_plain:.6f} learned {l_learned:.6f} gain {100 * gain:.2f}%")
+    # the network, trained on other random fields, lowers the loss on problems it has not seen
+    assert gain >= 0.05

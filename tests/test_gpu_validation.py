@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from gpu_util import dev, torch_cuda  # noqa: E402
+from gpu_util import dev, host, torch_cuda  # noqa: E402
 
 import workloads as W  # noqa: E402
 
@@ -137,3 +137,43 @@ class _hier:
         torch_cuda().cuda.synchronize()
         self.amg.amg_destroy(self.h)
         return False
+
+
+def test_cg_breakdown_reports_and_keeps_x(amg):
+    """CG on a symmetric indefinite matrix with a positive diagonal (1D chain, a_ii = 1,
+    a_i,i+1 = -2: eigenvalues 1 - 4 cos(j pi / (n + 1)), the smallest about -3): with b = M v,
+    v the eigenvector of the smallest eigenvalue, the l1-Jacobi preconditioner of degree 1 gives
+    z_0 = v, so (p_1, A p_1) = lambda_1 ||v||^2 < 0 at the first iteration.  The solve returns
+    AMG_EBREAKDOWN and leaves x at the last iterate (x0 = 0), finite.  The setup takes l1-Jacobi
+    sweeps on the coarsest level, so no factorisation sees the indefinite matrix."""
+    torch = torch_cuda()
+    n = 64
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        for j, v in ((i - 1, -2.0), (i, 1.0), (i + 1, -2.0)):
+            if 0 <= j < n:
+                cols.append(j)
+                vals.append(v)
+        rp[i + 1] = len(cols)
+    cl = np.array(cols)
+    vl = np.array(vals)
+    M = np.array([1.0 + 2.0 * ((i > 0) + (i < n - 1)) for i in range(n)])
+    v = np.sin(np.arange(1, n + 1) * np.pi / (n + 1))
+    b = M * v
+    h = amg.amg_setup(dev(rp.astype(np.int32)), dev(cl.astype(np.int32)), dev(vl), n, 1, 1, 1, 4096,
+                      amg.AMG_FP64, coarse_sweeps=4)
+    torch.cuda.synchronize()
+    try:
+        x = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        with pytest.raises(amg.AmgError) as e:
+            amg.pcg_solve_smoother(h, amg.AMG_L1JAC, 1, dev(b), x, True, 1e-8, 50)
+        assert e.value.code == amg.AMG_EBREAKDOWN
+        xh = host(x)
+        assert np.all(np.isfinite(xh)) and np.all(xh == 0.0)
+        # the flags are cleared by the next solve: a zero right-hand side returns at once
+        rc, it, rel, _ = amg.pcg_solve_smoother(h, amg.AMG_L1JAC, 1, dev(np.zeros(n)), x, True, 1e-8, 50)
+        assert rc == amg.AMG_OK and it == 0 and rel == 0.0
+    finally:
+        torch.cuda.synchronize()
+        amg.amg_destroy(h)
