@@ -332,9 +332,11 @@ int amg_learned_beta_grad(const amg_handle* h, int degree, const double* d_gbeta
  * ------------------------------------------------------------------------- */
 #define AMG_HBM_PARTIALS 16384
 /* Reads d_x[n] once (8 n bytes): d_partial[AMG_HBM_PARTIALS] receives block sums whose total
- * is sum_i x_i (rounding order fixed by the grid).  Asynchronous. */
+ * is sum_i x_i (rounding order fixed by the grid).  Asynchronous.  d_x must be 16-byte aligned;
+ * it may be NULL when n = 0 (the block sums are then zeros).  AMG_EINVAL otherwise. */
 int amg_hbm_read(const double* d_x, int64_t n, double* d_partial, void* stream);
-/* d_y[i] = d_x[i], i < n (8 n bytes read, 8 n written); the ranges must not overlap.  Asynchronous. */
+/* d_y[i] = d_x[i], i < n (8 n bytes read, 8 n written); the ranges must not overlap and both
+ * must be 16-byte aligned (AMG_EINVAL otherwise).  n = 0 does nothing.  Asynchronous. */
 int amg_hbm_copy(const double* d_x, double* d_y, int64_t n, void* stream);
 
 /* Human-readable name of a return code (static storage). */

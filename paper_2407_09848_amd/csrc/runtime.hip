@@ -1260,13 +1260,16 @@ int amg_learned_beta_grad(const amg_handle* h, int degree, const double* d_gbeta
 }
 
 int amg_hbm_read(const double* d_x, int64_t n, double* d_partial, void* stream) {
-  if (!d_x || !d_partial || n < 0 || (reinterpret_cast<uintptr_t>(d_x) & 15) != 0) return AMG_EINVAL;
+  // an empty array may come with a null pointer; the block sums are still written (zeros)
+  if (!d_partial || n < 0 || (n > 0 && !d_x) || (reinterpret_cast<uintptr_t>(d_x) & 15) != 0) return AMG_EINVAL;
   return amgp::launch_hbm_read((hipStream_t)stream, n, d_x, d_partial);
 }
 
 int amg_hbm_copy(const double* d_x, double* d_y, int64_t n, void* stream) {
-  if (!d_x || !d_y || n < 0 || ((reinterpret_cast<uintptr_t>(d_x) | reinterpret_cast<uintptr_t>(d_y)) & 15) != 0)
+  if (n < 0 || (n > 0 && (!d_x || !d_y)) ||
+      ((reinterpret_cast<uintptr_t>(d_x) | reinterpret_cast<uintptr_t>(d_y)) & 15) != 0)
     return AMG_EINVAL;
+  if (n == 0) return AMG_OK;
   const uintptr_t a = reinterpret_cast<uintptr_t>(d_x), b = reinterpret_cast<uintptr_t>(d_y);
   const uintptr_t bytes = (uintptr_t)n * sizeof(double);
   if (n > 0 && a < b + bytes && b < a + bytes) return AMG_EINVAL;
