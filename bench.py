@@ -1,27 +1,36 @@
-"""Benchmark: AMG-PCG on the 3D 7-point Poisson problem at 128^3 (one MI355X).
+"""Benchmark: AMG-PCG on the 27-point trilinear-FE Laplacian at 320^3 (one MI355X).
 
-A step is one complete solve A x = b to ||r|| <= 1e-8 ||b|| from x = 0 with
-the V-cycle preconditioner (box-aggregation hierarchy 128^3 -> 16^3, dense
-coarsest solve) smoothed by the optimal 4th-kind polynomial of degree 4, on
-a hierarchy already resident in HBM (setup excluded, reported separately).
+Workload (the largest configuration, 32.8M rows, 879M stored entries): A x = b
+with b uniform(-1, 1) from a seed, solved to ||r|| <= 1e-8 ||b|| from x = 0 by
+CG preconditioned with the V-cycle of the 2x2x2 box-aggregation hierarchy
+(320^3 -> 10^3, six levels, dense coarsest solve), smoothed by the optimal
+4th-kind polynomial of degree 4, all in FP64, on a hierarchy already resident
+in HBM (setup excluded, reported separately).  A step is one such solve.
 
-value       = algorithmic HBM bytes of the whole solve / its wall time (GB/s),
-              bytes summed from the per-kernel models below over the launches
-              one solve makes;
-roofline    = the fused recurrence-step kernel on the fine level, its
-              algorithmic bytes per launch / its average duration, timed here
-              with events on the launch stream (difference of degree-6 and
-              degree-2 smoother applications = 4 fused steps);
-cpu_baseline= the FP64 CPU oracle solving the same system once (host cores);
-variants    = time to 1e-8 of the other smoother kinds, of the FP32 hierarchy
-              inside FP64 CG, and (when a trained network is available) of the
-              learned beta, against the plain FP64 optimal 4th kind.
+value        = bytes one solve must move in the storage layouts the kernels use
+               (summed from the per-kernel models below over the launches of one
+               solve) / the solve's wall time, GB/s;
+roofline     = the fine-level fused recurrence step (k_fused<double,0,true,true,1>):
+               the bytes it must move per launch / its average duration, timed
+               here with events on the launch stream (degree-6 minus degree-3
+               smoother applications from x = 0 = three fused steps); beside it
+               the per-step figure of the CSR byte model (12 nnz + 60 n), and
+               the measured ceiling of this GPU (the library's plain read and
+               copy kernels);
+cpu_baseline = the FP64 CPU oracle applying the same smoother (degree 4, from
+               x = 0) to the fine level once, on one host thread, in GB/s of
+               the same byte model; its result is compared with the GPU's;
+variants     = time to 1e-8 of the other three variants of this workload (FP32
+               hierarchy inside FP64 CG, learned weights, optimal 1st kind),
+               of the remaining smoother kinds, and the FP32-against-FP64
+               comparison on the 256^3 variable-coefficient diffusion problem.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -32,223 +41,311 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Smoother HBM GB/s (% peak); AMG-PCG time to 1e-8 residual, learned/FP32 vs plain"
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
+KIND_NAMES = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
+FUSED_PROLONG_MAX_ROWS = 1 << 20  # box levels up to this size carry the prolongation in the smoother
 
 
-# ---- algorithmic byte models (float64 values, int32 indices) ----
-def b_fused(nnz, n, store=True, w=8):
-    # A (w + 4 per entry), gathered direction once, minv, r in, x read+write; + r out, g out
-    return (w + 4) * nnz + (w * 7 if store else w * 5) * n
+# ---------------------------------------------------------------------------
+# Byte models: the bytes each kernel must move in the layout it reads (values of w bytes,
+# int32 indices, gathered vectors counted once).  M is the matrix's bytes in its layout:
+# offset-aligned slices w per stored entry plus a 4-byte offset per 64, packed slices w + 4.
+# ---------------------------------------------------------------------------
+def matrix_bytes(amg, h, level, w):
+    padded, _, aligned = amg.amg_level_layout(h, level)
+    return padded * w + 4 * (padded // 64) if aligned else padded * (w + 4)
 
 
-def b_first_zero(n, store, mode, w=8):
-    return w * (2 + 1 + (1 if store else 0) + (1 if (store and mode == 1) else 0)) * n
+def level_table(amg, h, w):
+    """[(n, M, lanes)] for every level of handle h, with values of w bytes."""
+    out = []
+    for l in range(amg.amg_num_levels(h)):
+        n, _ = amg.amg_level_info(h, l)
+        out.append((n, matrix_bytes(amg, h, l, w), amg.amg_level_layout(h, l)[1]))
+    return out
 
 
-def b_first_res(nnz, n, w=8):
-    return (w + 4) * nnz + 5 * w * n
+def fused_bytes(n, M, w, store):
+    # reads minv, the gathered direction, r, x; writes x (+ r and the new direction)
+    return M + (7 if store else 5) * w * n
 
 
-def b_restrict(nnz, n, w=8):
-    return (w + 4) * nnz + 2 * w * n + 4 * n + w * n // 8
+def smooth_bytes(n, M, w, kind, k, from_zero, nc=0, prol=0):
+    """One smoother application of degree k; prol: 0 none, 1 carried by the first two kernels."""
+    if kind == 0:
+        if from_zero:
+            return 3 * w * n + (k - 1) * (M + 4 * w * n)
+        return k * (M + 4 * w * n) + (2 * w * n if k % 2 else 0)
+    if from_zero:
+        if k == 1:
+            return 3 * w * n
+        tot = M + (5 if k > 2 else 3) * w * n  # steps 1 and 2 merged (reads minv, b; writes x, r, g)
+        return tot + sum(fused_bytes(n, M, w, s < k - 3) for s in range(k - 2))
+    tot = M + 5 * w * n  # first step on x: reads b, x, minv; writes r, g
+    if prol:
+        tot += 8 * n + 2 * w * nc  # aggregate index and coarse value, in the first two kernels
+    if k == 1:
+        return tot + 3 * w * n
+    return tot + sum(fused_bytes(n, M, w, s < k - 2) for s in range(k - 1))
 
 
-def b_prolong(n, w=8):
-    return 2 * w * n + 4 * n + w * n // 8
-
-
-def vcycle_bytes(levels, ncp, nbatch, kind, k, w=8):
-    """Algorithmic bytes of one V-cycle (pre from zero, restrict, coarse, prolong, post)."""
+def vcycle_bytes(levels, w, kind, k, nbatch=1):
     tot = 0
-    mode = 1 if kind == 3 else 0
-    for (n, nnz) in levels[:-1]:
-        # pre-smoothing from zero
-        tot += b_first_zero(n, k > 1, mode, w) + max(k - 2, 0) * b_fused(nnz, n, True, w) + \
-            (b_fused(nnz, n, False, w) if k > 1 else 0)
-        tot += b_restrict(nnz, n, w) + b_prolong(n, w)
-        # post-smoothing from x
-        tot += b_first_res(nnz, n, w) + max(k - 2, 0) * b_fused(nnz, n, True, w) + \
-            (b_fused(nnz, n, False, w) if k > 1 else 2 * w * n + w * n)
-    nL = levels[-1][0]
-    nb = ncp // 64
-    # coarsest: the lower 64x64 blocks of the symmetric inverse once, the block partials written and read
-    tot += nbatch * (nb * (nb + 1) // 2) * 64 * 64 * 8 + 2 * nbatch * nb * nb * 64 * 8 + 2 * w * nL
+    for l, (n, M, lanes) in enumerate(levels[:-1]):
+        nc = levels[l + 1][0]
+        tot += smooth_bytes(n, M, w, kind, k, True)
+        if n > FUSED_PROLONG_MAX_ROWS:  # residual, then restriction over 8 children
+            tot += M + 3 * w * n + w * n + 32 * nc + w * nc
+        else:
+            tot += M + 2 * w * n + 32 * nc + w * nc
+        fused = kind != 0 and lanes == 1 and n <= FUSED_PROLONG_MAX_ROWS
+        if not fused:
+            tot += 2 * w * n + 4 * n + w * nc
+        tot += smooth_bytes(n, M, w, kind, k, False, nc, 1 if fused else 0)
+    nL = levels[-1][0] // nbatch
+    nb = (nL + 63) // 64
+    # coarsest: the packed lower 64 x 64 tiles of the inverse once, the tile partials written and read
+    tot += nbatch * (nb * (nb + 1) // 2 * 64 * 64 * 8 + 2 * nb * nb * 64 * 8) + 2 * w * levels[-1][0]
     return tot
 
 
-def pcg_bytes(levels, ncp, nbatch, kind, k, iters, w=8):
-    n, nnz = levels[0]
-    # SpMV with the fused direction update (gathers z and p_old, writes p and q), x/r update with (r, r),
-    # the V-cycle, and (r, z)
-    per_it = (12 * nnz + 32 * n) + 48 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n
-    if w == 4:
-        per_it += 12 * n  # casts r -> f32, z -> f64
-    # x = 0, r = b, the first V-cycle, (r, z), p_old = 0
-    setup = 8 * n + 16 * n + vcycle_bytes(levels, ncp, nbatch, kind, k, w) + 16 * n + 8 * n
-    return setup + iters * per_it
+def solve_bytes(levels, M0_64, w, kind, k, iters, flexible):
+    """One PCG solve from x = 0: b checks and copies, then per iteration the CG product with the
+    direction update, the x / r update, one V-cycle (FP32: with the casts) and its dot products."""
+    n = levels[0][0]
+    wz = w  # the CG kernels read the hierarchy's own output
+    vc = vcycle_bytes(levels, w, kind, k) + (12 * n if w == 4 else 0)
+    dots = (8 + wz) * n + (8 * n if flexible else 0)
+    per_it = (M0_64 + (24 + wz) * n) + (48 + (8 if flexible else 0)) * n + vc + dots
+    return 48 * n + iters * per_it
 
 
-def measured_traffic(size):
-    """HBM bytes per launch of the fine-level fused step from the committed rocprofv3 counter
-    summary, or None when that summary does not cover this workload or the kernel source
-    has changed since the counters were taken."""
-    import hashlib
-    import re
-    path = os.path.join(ROOT, "profiles", f"fused_step_poisson{size}.md")
-    if not os.path.exists(path):
-        return None
+def csr_model_step(nnz, n):
+    """The per-step figure of the CSR model: 12 bytes per stored entry plus 60 per row."""
+    return 12 * nnz + 60 * n
+
+
+def cpu_description():
+    model = platform.processor() or ""
     try:
-        src = open(os.path.join(ROOT, "paper_2407_09848_amd", "csrc", "kernels_sparse.hip")).read()
-        a = src.index("\n", src.index("// BEGIN fused-step")) + 1
-        digest = hashlib.sha256(src[a:src.index("// END fused-step")].encode()).hexdigest()[:16]
-        prof = open(path).read()
-        if re.search(r"sha256 prefix: (\w+)", prof).group(1) != digest:
-            return None
-        return int(re.search(r"traffic_bytes_per_launch: (\d+)", prof).group(1))
-    except (OSError, ValueError, AttributeError):
-        return None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
-def stacked_diffusion(W, nprob, size, seed0):
-    import numpy as np
-    sig = W.config4_sigmas(nprob)
-    mats = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((size, size, size), 8.0, seed0 + p)))
-            for p in range(nprob)]
-    return W.stack_block_diagonal(mats), sig
+# ---------------------------------------------------------------------------
+# helpers on the GPU
+# ---------------------------------------------------------------------------
+def event_time(stream, fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
 
 
-def learned_variant(args, amg, W, h, bd, x, stream, variants):
-    """Train the 8-64-64-6 network on 32 stacked 64^3 diffusion problems (the learned-weights
-    workload, FP32, the library's adjoint and network kernels), report its loss against the plain
-    optimal weights at degree 6 and at the bench degree, then apply the bench-degree network to
-    this system (kept only if it lowers the two-cycle residual ratio here) and time the solve."""
-    import numpy as np
+def true_relres(amg, h, bd, x):
+    """||b - A x|| / ||b|| with the library's level-0 product (a check, not part of the path)."""
+    import torch
+    y = torch.empty_like(x)
+    amg.amg_spmv(h, 0, x, y)
+    torch.cuda.synchronize()
+    return float(torch.linalg.norm(bd - y) / torch.linalg.norm(bd))
+
+
+def ceiling(amg, stream):
+    """Plain read and copy of this GPU through the library's bandwidth kernels (16-byte
+    nontemporal accesses): a 4 GiB read, a 2 GiB -> 2 GiB copy."""
+    import torch
+    x = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    part = torch.empty(amg.AMG_HBM_PARTIALS, dtype=torch.float64, device="cuda")
+    amg.amg_hbm_read(x, part)
+    t_read, _ = event_time(stream, lambda: amg.amg_hbm_read(x, part), 10)
+    half = x.numel() // 2
+    src, dst = x[:half], x[half:]
+    amg.amg_hbm_copy(src, dst)
+    t_copy, _ = event_time(stream, lambda: amg.amg_hbm_copy(src, dst), 10)
+    torch.cuda.synchronize()
+    out = {"read_GBps": round(x.numel() * 8 / (t_read * 1e-3) / 1e9, 1),
+           "copy_GBps": round(2 * half * 8 / (t_copy * 1e-3) / 1e9, 1),
+           "kernels": "amg_hbm_read (4 GiB), amg_hbm_copy (2 GiB to 2 GiB)"}
+    del x, part
+    return out
+
+
+# ---------------------------------------------------------------------------
+# learned weights on the 27-point family
+# ---------------------------------------------------------------------------
+def train_learned(args, amg, W):
+    """Train the 8-64-64-6 network (FP32, the library's adjoint and network kernels) on the
+    27-point family (stacks of 40^3 and 80^3 problems) and on stacked 64^3 diffusion problems,
+    Adam steps alternating between the three sets; report the loss of the plain and the
+    learned weights on each set and on held-out problems (a 160^3 27-point problem and 32
+    further diffusion problems)."""
     import torch
 
     from paper_2407_09848_amd import learned
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    out = {}
-    t0 = time.perf_counter()
-    big, sig = stacked_diffusion(W, 32, 64, W.SEED_GRF)
-    held, _ = stacked_diffusion(W, 32, 64, W.SEED_GRF + 500)
-    b4 = dev(W.rhs_uniform(big.n, W.SEED_RHS + 4))
-    b4h = dev(W.rhs_uniform(held.n, W.SEED_RHS + 40))
-    hs = [amg.amg_setup(dev(M.row_ptr), dev(M.col), dev(M.val), M.grid[0], M.grid[1], M.grid[2] // 32, 32,
-                        4096, amg.AMG_FP32) for M in (big, held)]
-    out["setup_s"] = round(time.perf_counter() - t0, 2)
-    nets = {}
-    for deg in sorted({6, args.degree}):
-        t0 = time.perf_counter()
-        res = learned.train(hs[0], b4, sig, degree=deg, steps=args.train_steps, lr=3e-3,
-                            init_params=W.mlp_init(W.SEED_MLP))
-        torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
-        f = amg.amg_level_features(hs[0], deg, sig)
-        beta, _, valid = learned.predict_beta(hs[0], res.params, f, deg, 32)
-        lt, _ = learned.evaluate(hs[0], beta, b4, deg, 32)
-        fh = amg.amg_level_features(hs[1], deg, sig)
-        bh, _, _ = learned.predict_beta(hs[1], res.params, fh, deg, 32)
-        L = amg.amg_num_levels(hs[1])
-        plain = dev(np.tile(np.array(amg.amg_default_beta(deg)), (32, L, 1)).ravel())
-        lh, _ = learned.evaluate(hs[1], bh, b4h, deg, 32)
-        lp, _ = learned.evaluate(hs[1], plain, b4h, deg, 32)
-        out[f"degree{deg}"] = {"train_steps": args.train_steps, "train_s": round(tt, 2),
-                               "train_loss_plain": round(res.plain_loss, 6), "train_loss_learned": round(lt, 6),
-                               "heldout_loss_plain": round(lp, 6), "heldout_loss_learned": round(lh, 6),
-                               "invalid_rows": int((valid == 0).sum().item())}
-        nets[deg] = res.params
-    for hh in hs:
-        amg.amg_destroy(hh)
-    # apply to this system at the bench degree, kept only if it lowers the two-cycle residual ratio here
     deg = args.degree
-    lb = learned.learned_level_betas(h, nets[deg], deg, 0.0)
-    L = amg.amg_num_levels(h)
-    tab_l = np.array(amg.amg_default_beta(deg) * L).reshape(L, deg)
-    tab_l[:L - 1] = np.array(lb)
-    plain = dev(np.tile(np.array(amg.amg_default_beta(deg)), (L, 1)).ravel())
-    r_learned, _ = learned.evaluate(h, dev(tab_l.ravel()), bd, deg, 1)
+    t0 = time.perf_counter()
+
+    def stack(mats, seed, prec=amg.AMG_FP32):
+        big = W.stack_block_diagonal(mats)
+        h = amg.amg_setup(dev(big.row_ptr), dev(big.col), dev(big.val), big.grid[0], big.grid[1],
+                          big.grid[2] // len(mats), len(mats), 4096, prec)
+        return h, dev(W.rhs_uniform(big.n, seed))
+
+    sets = []
+    q40 = stack([W.q1_27pt(40)] * 8, W.SEED_RHS + 50)
+    q80 = stack([W.q1_27pt(80)] * 2, W.SEED_RHS + 51)
+    sig = W.config4_sigmas(32)
+    diff = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((64,) * 3, 8.0, W.SEED_GRF + p)))
+            for p in range(32)]
+    dh = stack(diff, W.SEED_RHS + 4)
+    sets = [(q40, [0.0] * 8), (q80, [0.0] * 2), (dh, list(sig))]
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = learned.train([s[0][0] for s in sets], [s[0][1] for s in sets], [s[1] for s in sets], degree=deg,
+                        steps=args.train_steps, lr=3e-3, init_params=W.mlp_init(W.SEED_MLP))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"degree": deg, "train_steps": args.train_steps, "setup_s": round(setup_s, 2),
+           "train_s": round(train_s, 2), "invalid_rows_last_step": res.invalid_rows,
+           "train_sets": {name: {"loss_plain": round(p, 6), "loss_learned": round(f, 6)}
+                          for name, p, f in zip(("q1_27pt_8x40^3", "q1_27pt_2x80^3", "diffusion_32x64^3"),
+                                                res.plain_loss_per_set, res.final_loss_per_set)}}
+    for (h, _), _s in sets:
+        amg.amg_destroy(h)
+    # held out: a 160^3 27-point problem, 32 further diffusion problems
+    held = {}
+    h160, b160 = stack([W.q1_27pt(160)], W.SEED_RHS + 52, amg.AMG_FP64)
+    held["q1_27pt_160^3"] = heldout_loss(amg, learned, h160, b160, res.params, deg, [0.0])
+    amg.amg_destroy(h160)
+    diff2 = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((64,) * 3, 8.0, W.SEED_GRF + 500 + p)))
+             for p in range(32)]
+    hd2, bd2 = stack(diff2, W.SEED_RHS + 40)
+    held["diffusion_32x64^3"] = heldout_loss(amg, learned, hd2, bd2, res.params, deg, list(sig))
+    amg.amg_destroy(hd2)
+    out["heldout"] = held
+    return res.params, out
+
+
+def heldout_loss(amg, learned, h, b, params, deg, sigmas):
+    f = amg.amg_level_features(h, deg, sigmas)
+    beta, _, valid = learned.predict_beta(h, params, f, deg, len(sigmas))
+    lp, _ = learned.evaluate(h, learned.plain_beta(h, deg, len(sigmas)), b, deg, len(sigmas))
+    ll, _ = learned.evaluate(h, beta, b, deg, len(sigmas))
+    return {"loss_plain": round(lp, 6), "loss_learned": round(ll, 6), "fallback_rows": learned.count_fallbacks(valid)}
+
+
+def learned_variant(args, amg, W, h, bd, x, stream, params):
+    """Apply the trained network per level to this hierarchy; the learned weights are kept
+    when they lower the two-cycle residual ratio of this right-hand side (else the plain
+    weights: the fallback); time the solve."""
+    import torch
+
+    from paper_2407_09848_amd import learned
+    deg = args.degree
+    lb = learned.learned_level_betas(h, params, deg, 0.0)
+    plain = learned.plain_beta(h, deg, 1)
+    r_learned, _ = learned.evaluate(h, learned.with_level_betas(plain, lb), bd, deg, 1)
     r_plain, _ = learned.evaluate(h, plain, bd, deg, 1)
     use = r_learned < r_plain
     if use:
         learned.apply_level_betas(h, deg, lb)
     amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(3):
-        rc, itv, relv, _ = amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    tm, (rc, itv, _, _) = event_time(stream, lambda: amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000), 2)
+    rr = true_relres(amg, h, bd, x)
     amg.amg_reset_beta(h)
-    tm = e0.elapsed_time(e1) / 3
-    base = variants.get(f"fp64_optcheb4_k{deg}", {}).get("ms")
-    variants[f"learned_optcheb4_k{deg}"] = {"ms": round(tm, 3), "iters": itv,
-                                           "vs_plain_fp64": round(tm / base, 3) if base else None,
-                                           "weights": "learned" if use else "plain (fallback)"}
-    out["this_system"] = {"two_cycle_ratio_plain": round(r_plain, 6), "two_cycle_ratio_learned": round(r_learned, 6),
-                          "weights_used": "learned" if use else "plain (fallback)", "level_betas": lb}
-    out["heldout_solves"] = heldout_solves(args, amg, W, nets[deg], deg, stream)
+    return {"ms": round(tm, 3), "iters": itv, "true_relres": rr, "weights": "learned" if use else "plain (fallback)",
+            "two_cycle_ratio_plain": round(r_plain, 6), "two_cycle_ratio_learned": round(r_learned, 6),
+            "level_betas": [[round(v, 6) for v in row] for row in lb]}
+
+
+def c3_variant(amg, W, stream):
+    """The 256^3 variable-coefficient diffusion problem (sigma = 1): FP64 and FP32 hierarchy,
+    optimal 4th kind, k = 4, time to 1e-8 and the difference of the two solutions."""
+    import torch
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    t0 = time.perf_counter()
+    A, b, _ = W.config_problem(3)
+    asm = time.perf_counter() - t0
+    rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
+    out = {"workload": "fv_diffusion_7pt_256^3_sigma1", "n": A.n, "nnz": A.nnz, "assembly_s": round(asm, 2)}
+    xs = {}
+    for prec, name in ((amg.AMG_FP64, "fp64"), (amg.AMG_FP32, "fp32")):
+        t0 = time.perf_counter()
+        h = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, prec)
+        torch.cuda.synchronize()
+        st = time.perf_counter() - t0
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        flex = prec == amg.AMG_FP32
+        amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 1000, flex)
+        tm, (rc, it, _, _) = event_time(stream, lambda: amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 1000, flex), 3)
+        out[name] = {"ms": round(tm, 3), "iters": it, "setup_s": round(st, 3),
+                     "true_relres": true_relres(amg, h, bd, x)}
+        xs[name] = x
+        amg.amg_destroy(h)
+    out["fp32_vs_fp64_time"] = round(out["fp32"]["ms"] / out["fp64"]["ms"], 3)
+    out["fp32_vs_fp64_solution_relerr"] = float(torch.linalg.norm(xs["fp32"] - xs["fp64"]) /
+                                                torch.linalg.norm(xs["fp64"]))
     return out
 
 
-def heldout_solves(args, amg, W, params, deg, stream):
-    """Time to 1e-8 on held-out problems of the training family (one 64^3 diffusion problem per
-    sigma, FP64 hierarchy, standard PCG), plain optimal weights against the learned ones (kept only
-    where they lower the two-cycle residual ratio of the problem's right-hand side)."""
-    import numpy as np
-    import torch
+def cpu_baseline(args, A, b, x_gpu, gpu_apply_ms, apply_bytes):
+    """The oracle's smoother application (optimal 4th kind, degree args.degree, from x = 0) on the
+    fine level, one host thread; the l1 diagonal is computed beforehand and not timed."""
+    from threadpoolctl import threadpool_limits
 
-    from paper_2407_09848_amd import learned
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    res = {}
-    for idx, sigma in enumerate((0.5, 1.0, 2.0)):
-        M = W.fv_diffusion(np.exp(sigma * W.gaussian_random_field((64, 64, 64), 8.0, W.SEED_GRF + 900 + idx)))
-        b = dev(W.rhs_uniform(M.n, W.SEED_RHS + 90 + idx))
-        hp = amg.amg_setup(dev(M.row_ptr), dev(M.col), dev(M.val), *M.grid, 1, 4096, amg.AMG_FP64)
-        x = torch.zeros(M.n, dtype=torch.float64, device="cuda")
-        L = amg.amg_num_levels(hp)
-        lb = learned.learned_level_betas(hp, params, deg, sigma)
-        tab = np.array(amg.amg_default_beta(deg) * L).reshape(L, deg)
-        tab[:L - 1] = np.array(lb)
-        r_l, _ = learned.evaluate(hp, dev(tab.ravel()), b, deg, 1)
-        r_p, _ = learned.evaluate(hp, dev(np.tile(np.array(amg.amg_default_beta(deg)), (L, 1)).ravel()), b, deg, 1)
-        entry = {"two_cycle_ratio_plain": round(r_p, 6), "two_cycle_ratio_learned": round(r_l, 6)}
-        for name, use in (("plain", False), ("learned", r_l < r_p)):
-            amg.amg_reset_beta(hp)
-            if use:
-                learned.apply_level_betas(hp, deg, lb)
-            amg.pcg_solve(hp, args.kind, deg, b, x, True, 1e-8, 1000)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(3):
-                rc, itv, _, _ = amg.pcg_solve(hp, args.kind, deg, b, x, True, 1e-8, 1000)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            entry[name] = {"ms": round(e0.elapsed_time(e1) / 3, 3), "iters": itv}
-            if name == "learned":
-                entry[name]["weights"] = "learned" if use else "plain (fallback)"
-        entry["learned_vs_plain"] = round(entry["learned"]["ms"] / entry["plain"]["ms"], 3)
-        amg.amg_destroy(hp)
-        res[f"sigma{sigma}"] = entry
-    return res
+    from oracle import polynomials as P
+    from oracle import smoothers as S
+    model, ncpu = cpu_description()
+    with threadpool_limits(limits=1):
+        As = A.to_scipy()
+        t0 = time.perf_counter()
+        Minv = S.l1_diagonal(As)
+        l1_s = time.perf_counter() - t0
+        beta = P.optimal_beta(args.degree)[0] if args.kind == 2 else None
+        a = P.a_star(args.degree) if args.kind == 3 else None
+        t0 = time.perf_counter()
+        xo = S.smooth(As, Minv, b, None, args.kind, args.degree, beta, a)
+        cpu_s = time.perf_counter() - t0
+    err = float(np.max(np.abs(x_gpu - xo)) / np.max(np.abs(xo)))
+    return {"value": round(apply_bytes / cpu_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle application of the {KIND_NAMES[args.kind]} smoother of degree "
+                      f"{args.degree} from x = 0 on the {A.grid[0]}^3 fine level ({A.n} rows; {cpu_s:.1f} s, "
+                      f"scipy/numpy on one thread), GB/s of the same byte model as the GPU application",
+            "apply_s": round(cpu_s, 3), "l1_diagonal_s_untimed": round(l1_s, 2), "host_cpu_model": model,
+            "host_cpu_count": ncpu, "gpu_same_apply_ms": round(gpu_apply_ms, 3),
+            "gpu_vs_oracle_max_abs_err_rel": err}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=320)
     ap.add_argument("--kind", type=int, default=2)
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variants", default="kinds,fp32,paper",
-                    help="comma-separated subset of the variants to time: kinds (the other smoother kinds), "
-                         "fp32 (the FP32 hierarchy), paper (smoothed prolongators on box, matching and VBM "
-                         "aggregates)")
-    ap.add_argument("--no-learned", action="store_true", help="skip training the learned-weight network")
-    ap.add_argument("--train-steps", type=int, default=100)
+    ap.add_argument("--variants", default="fp32,learned,kinds,c3",
+                    help="comma-separated subset of the variants to time: fp32 (the FP32 hierarchy), learned "
+                         "(the trained network's weights), kinds (the other smoother kinds), c3 (FP32 against "
+                         "FP64 on the 256^3 diffusion problem); empty for none")
+    ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--counter-sample", action="store_true",
+                    help="setup, three smoother applications of degree 6 on the fine level and one 1 GiB copy "
+                         "through the library's copy kernel, then exit (the program the HBM byte counters are "
+                         "read on)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1).",
@@ -261,19 +358,31 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    A, b, _ = W.config_problem(2, size=args.size)
+    t0 = time.perf_counter()
+    A, b, _ = W.config_problem(5, size=args.size)
+    assembly_s = time.perf_counter() - t0
     rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    L = amg.amg_num_levels(h)
-    levels = [amg.amg_level_info(h, l) for l in range(L)]
-    nL = levels[-1][0]
-    ncp = (nL + 63) // 64 * 64
-    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    n0, nnz0 = amg.amg_level_info(h, 0)
+    x = torch.zeros(n0, dtype=torch.float64, device="cuda")
+
+    if args.counter_sample:
+        xs = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            amg.smoother_apply(h, 0, args.kind, 6, bd, xs, True)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        amg.amg_hbm_copy(src, dst)
+        torch.cuda.synchronize()
+        amg.amg_destroy(h)
+        print(json.dumps({"counter_sample": True, "n": n0, "copy_bytes_each_way": src.numel() * 8}), flush=True)
+        return
 
     def solve(handle, kind, k, flexible=False):
         return amg.pcg_solve(handle, kind, k, bd, x, True, 1e-8, 1000, flexible)
@@ -281,178 +390,134 @@ def main():
     for _ in range(args.warmup):
         solve(h, args.kind, args.degree)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    iters = []
-    for _ in range(args.steps):
-        rc, it, rel, _ = solve(h, args.kind, args.degree)
-        iters.append(it)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    it = iters[-1]
-    # the solve once more, untimed, for its residual history and solution
+    ms, (rc, it, rel, _) = event_time(stream, lambda: solve(h, args.kind, args.degree), args.steps)
+    # once more, untimed, for the residual history and the solution
     _, _, _, hist = amg.pcg_solve(h, args.kind, args.degree, bd, x, True, 1e-8, 1000, False, True)
-    x_gpu = x.cpu().numpy()
     solve_info = {"iters": len(hist) - 1, "relres_history": [float(f"{v:.4e}") for v in hist],
-                  "true_relres": float(np.linalg.norm(b - A.to_scipy() @ x_gpu) / np.linalg.norm(b))}
-    solve_bytes = pcg_bytes(levels, ncp, 1, args.kind, args.degree, it)
-    value = solve_bytes / (ms * 1e-3) / 1e9
+                  "true_relres": true_relres(amg, h, bd, x)}
+    L = amg.amg_num_levels(h)
+    lv64 = level_table(amg, h, 8)
+    M0 = lv64[0][1]
+    value = solve_bytes(lv64, M0, 8, args.kind, args.degree, it, False) / (ms * 1e-3) / 1e9
 
-    # ---- fused recurrence step on the fine level: events around smoother applications ----
-    n0, nnz0 = levels[0]
+    # ---- the fine level's fused step: degree 6 minus degree 3 from x = 0 = three stored steps ----
     xs = torch.zeros(n0, dtype=torch.float64, device="cuda")
-    reps = 50
+    reps = 10
 
     def time_apply(k):
-        for _ in range(3):
+        for _ in range(2):
             amg.smoother_apply(h, 0, args.kind, k, bd, xs, True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            amg.smoother_apply(h, 0, args.kind, k, bd, xs, True)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        t, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, args.kind, k, bd, xs, True), reps)
+        return t
 
-    t6, t2 = time_apply(6), time_apply(2)
-    t_fused_ms = (t6 - t2) / 4.0
-    fused_bytes = b_fused(nnz0, n0, True)
-    achieved = fused_bytes / (t_fused_ms * 1e-3) / 1e9
-    # the bytes the kernel must move in the layout it uses: offset-aligned slices read no column
-    # indices (8 bytes per stored entry plus a 4-byte offset per 64), packed ones 12
+    t6, t3 = time_apply(6), time_apply(3)
+    t_step = (t6 - t3) / 3.0
+    step_bytes = fused_bytes(n0, M0, 8, True)
+    achieved = step_bytes / (t_step * 1e-3) / 1e9
     padded, lanes, aligned = amg.amg_level_layout(h, 0)
-    format_bytes = (8 * padded + 4 * (padded // 64) if aligned else 12 * padded) + 56 * n0
-    achieved_fmt = format_bytes / (t_fused_ms * 1e-3) / 1e9
+    csr_bytes = csr_model_step(nnz0, n0)
+    ceil = ceiling(amg, stream)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM, 4), "traffic": measured_traffic(args.size),
-                "kernel": f"k_fused<double,0,true> (fine level, {args.size}^3)",
-                "bytes_per_launch": fused_bytes, "avg_launch_us": round(t_fused_ms * 1e3, 2),
+                "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
+                "kernel": f"k_fused<double,0,true,true,1> (fine level, {args.size}^3, 27-point)",
+                "bytes_per_launch": int(step_bytes), "avg_launch_us": round(t_step * 1e3, 2),
                 "layout": {"stored_entries": int(padded), "lanes_per_row": lanes, "offset_aligned": aligned,
-                           "format_bytes_per_launch": int(format_bytes),
-                           "achieved_format": round(achieved_fmt, 1),
-                           "frac_format": round(achieved_fmt / PEAK_HBM, 4)}}
+                           "bytes_per_launch": "8 per stored entry + 4 per 64 + 56 per row"},
+                "csr_model": {"bytes_per_launch": int(csr_bytes), "formula": "12 nnz + 60 n",
+                              "GBps": round(csr_bytes / (t_step * 1e-3) / 1e9, 1),
+                              "note": "counts column indices and row pointers the offset-aligned layout "
+                                      "does not read"},
+                "ceiling": ceil, "frac_of_read_ceiling": round(achieved / ceil["read_GBps"], 4)}
+    traffic = measured_traffic(args.size)
+    if traffic is not None:
+        roofline["traffic"] = traffic
 
-    # ---- plain device copy of 1 GiB: measured copy bandwidth, and the reference
-    #      dispatch that calibrates the HBM byte counters of a profiling run ----
-    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        dst.copy_(src)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    roofline["copy_GBps"] = round(copy_gbs, 1)
-    del dst
-    src2 = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB read by a reduction
-    src2.sum()
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(10):
-        src2.sum()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    roofline["read_GBps"] = round(src2.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-    del src, src2
+    # ---- variants ----
+    chosen = {v for v in args.variants.split(",") if v}
+    variants = {f"fp64_{KIND_NAMES[args.kind]}_k{args.degree}": {"ms": round(ms, 3), "iters": it}}
+    base = ms
 
-    # ---- variants: other kinds, FP32 hierarchy ----
-    variants = {}
-    chosen = set(args.variants.split(","))
-    if not args.no_variants:
-        def time_solve(handle, kind, k, reps=3, flexible=False):
-            solve(handle, kind, k, flexible)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                rc, itv, relv, _ = solve(handle, kind, k, flexible)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps, itv
-        names = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
-        for kind in ((0, 1, 2, 3) if "kinds" in chosen else (args.kind,)):
-            tm, itv = time_solve(h, kind, args.degree)
-            variants[f"fp64_{names[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv}
-        if "fp32" in chosen:
-            h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
-            tm, itv = time_solve(h32, args.kind, args.degree)
-            xr = x.cpu().numpy()
-            variants[f"fp32_{names[args.kind]}_k{args.degree}"] = {
-                "ms": round(tm, 3), "iters": itv,
-                "true_relres": float(np.linalg.norm(b - A.to_scipy() @ xr) / np.linalg.norm(b))}
-            amg.amg_destroy(h32)
-        # the paper's own preconditioner ingredients (Section 4): smoothed prolongator,
-        # 30 l1-Jacobi sweeps on the coarsest level, flexible CG
-        # (on the box aggregates, on compatible-matching aggregates of up to 8 rows and on the
-        # classical smoothed-aggregation (VBM) aggregates with strength threshold 0.08), and the
-        # smoothed prolongator with the dense Cholesky coarsest solve of the plain configuration
-        paper = (("box", amg.AMG_AGG_BOX, 30), ("matching", amg.AMG_AGG_MATCHING, 30),
-                 ("vbm", amg.AMG_AGG_VBM, 30), ("box", amg.AMG_AGG_BOX, 0))
-        for tag, agg, sweeps in (paper if "paper" in chosen else ()):
-            name = f"{tag}_smoothed_p_" + (f"sweeps{sweeps}_fcg" if sweeps else "cholesky_fcg")
-            t0 = time.perf_counter()
-            try:
-                hsa = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64, 2, True, sweeps, agg)
-            except amg.AmgError as e:
-                hsa = None
-                variants[name] = {"error": str(e)}
-            if hsa is None:
-                continue
-            torch.cuda.synchronize()
-            sa_setup = time.perf_counter() - t0
-            for kind in (args.kind, 3):
-                tm, itv = time_solve(hsa, kind, args.degree, flexible=True)
-                variants[f"fp64_{names[kind]}_k{args.degree}_{name}"] = {
-                    "ms": round(tm, 3), "iters": itv, "setup_s": round(sa_setup, 3),
-                    "levels": [amg.amg_level_info(hsa, l) for l in range(amg.amg_num_levels(hsa))]}
-            amg.amg_destroy(hsa)
-        base = variants[f"fp64_{names[args.kind]}_k{args.degree}"]["ms"]
-        for v in variants.values():
-            if "ms" in v:
-                v["vs_plain_fp64"] = round(v["ms"] / base, 3)
-    # ---- learned weights: trained on the stacked diffusion problems, applied to this system ----
+    def time_solve(handle, kind, k, flexible=False, reps=2):
+        solve(handle, kind, k, flexible)
+        torch.cuda.synchronize()
+        tm, (rcv, itv, _, _) = event_time(stream, lambda: solve(handle, kind, k, flexible), reps)
+        return tm, itv
+
+    other_kinds = (3,) if args.kind != 3 else (2,)
+    if "kinds" in chosen:
+        other_kinds = tuple(kd for kd in (3, 1, 0) if kd != args.kind)
+    for kind in other_kinds:
+        tm, itv = time_solve(h, kind, args.degree)
+        variants[f"fp64_{KIND_NAMES[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv,
+                                                              "true_relres": true_relres(amg, h, bd, x)}
+    if "fp32" in chosen:
+        t0 = time.perf_counter()
+        h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
+        torch.cuda.synchronize()
+        s32 = time.perf_counter() - t0
+        tm, itv = time_solve(h32, args.kind, args.degree, flexible=True)
+        variants[f"fp32_{KIND_NAMES[args.kind]}_k{args.degree}"] = {
+            "ms": round(tm, 3), "iters": itv, "setup_s": round(s32, 3), "outer": "FP64 flexible CG",
+            "true_relres": true_relres(amg, h, bd, x)}
+        amg.amg_destroy(h32)
     learned_info = None
-    if not args.no_variants and not args.no_learned:
-        learned_info = learned_variant(args, amg, W, h, bd, x, stream, variants)
-    amg.amg_destroy(h)
+    if "learned" in chosen and args.kind == 2:
+        params, learned_info = train_learned(args, amg, W)
+        variants[f"learned_{KIND_NAMES[args.kind]}_k{args.degree}"] = learned_variant(args, amg, W, h, bd, x,
+                                                                                    stream, params)
+    for v in variants.values():
+        v["vs_plain_fp64"] = round(v["ms"] / base, 3)
+    c3 = c3_variant(amg, W, stream) if "c3" in chosen else None
 
-    # ---- CPU baseline: the oracle solving the same system once ----
+    # ---- CPU baseline: the oracle's smoother application on the same fine level ----
     cpu = None
     if not args.no_cpu:
-        from threadpoolctl import threadpool_limits
-
-        from oracle import amg as OA
-        with threadpool_limits(limits=1):
-            As = A.to_scipy()
-            H = OA.build_hierarchy(As, A.grid)
-            t0 = time.perf_counter()
-            res, _ = OA.amg_pcg(As, b, A.grid, args.kind, args.degree, H=H)
-            cpu_s = time.perf_counter() - t0
-        cpu_bytes = pcg_bytes(levels, ncp, 1, args.kind, args.degree, res.iters)
-        cpu = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full FP64 oracle AMG-PCG solve of the same {args.size}^3 system "
-                         f"({res.iters} iterations, {cpu_s:.1f} s, scipy/numpy single thread)",
-               "solve_s": round(cpu_s, 2), "iters": res.iters}
-        solve_info["error_vs_oracle"] = float(np.linalg.norm(x_gpu - res.x) / np.linalg.norm(res.x))
-        solve_info["iters_oracle"] = res.iters
+        xs.zero_()
+        amg.smoother_apply(h, 0, args.kind, args.degree, bd, xs, True)
+        t_apply, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, args.kind, args.degree, bd, xs, True), 5)
+        apply_bytes = smooth_bytes(n0, M0, 8, args.kind, args.degree, True)
+        x_gpu = xs.cpu().numpy()
+        amg.amg_destroy(h)
+        h = None
+        del rp, cl, vl
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(args, A, b, x_gpu, t_apply, apply_bytes)
+    if h is not None:
+        amg.amg_destroy(h)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"poisson3d_7pt_{args.size}^3_amg_pcg_to_1e-8",
-                   "smoother": {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}[args.kind],
-                   "degree": args.degree, "n": int(n0), "nnz": int(nnz0), "levels": [int(l[0]) for l in levels],
-                   "iters": it, "setup_s": round(setup_s, 3)},
+        "config": {"workload": f"q1_27pt_{args.size}^3_amg_pcg_to_1e-8",
+                   "smoother": KIND_NAMES[args.kind], "degree": args.degree, "n": int(n0), "nnz": int(nnz0),
+                   "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2),
+                   "setup_s": round(setup_s, 3)},
         "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
-        "learned": learned_info,
+        "learned": learned_info, "diffusion_256": c3,
     }
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(size):
+    """HBM bytes per launch of the fine-level fused step from the committed rocprofv3 counter
+    summary of this workload, or None when there is none or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"fused_step_q1_{size}.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        src = open(os.path.join(ROOT, "paper_2407_09848_amd", "csrc", "kernels_sparse.hip")).read()
+        a = src.index("\n", src.index("// BEGIN fused-step")) + 1
+        digest = hashlib.sha256(src[a:src.index("// END fused-step")].encode()).hexdigest()[:16]
+        prof = open(path).read()
+        if re.search(r"sha256 prefix: (\w+)", prof).group(1) != digest:
+            return None
+        return int(re.search(r"traffic_bytes_per_launch: (\d+)", prof).group(1))
+    except (OSError, ValueError, AttributeError):
+        return None
 
 
 if __name__ == "__main__":

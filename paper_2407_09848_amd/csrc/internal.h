@@ -32,11 +32,11 @@ constexpr int64_t kAlignedWideMinRows = int64_t(1) << 18;
 // step t of slice s holds the entries of offset doff[sptr[s] / 64 + t] for all
 // its rows (0 where a row has none), so the kernels form the column as
 // row + offset, clamped into [0, n), and read no column indices: 8 instead of
-// 12 bytes per stored FP64 entry.  `col` is still filled (with the same clamped
-// columns) for code that reads it.  The FP32 copy of offset-aligned slices keeps
-// each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit at 128 q + 2 l and
-// 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so that one 8-byte
-// load per lane serves two steps; `col` keeps the unpaired order.
+// 12 bytes per stored FP64 entry (`col` is null).  Each lane's steps are kept in
+// pairs: steps 2q and 2q + 1 of lane l sit at 128 q + 2 l and 128 q + 2 l + 1 of
+// the slice (an odd last step t at 64 t + l), so that one 16-byte (FP64) or
+// 8-byte (FP32) load per lane serves two steps; the FP32 copy keeps the
+// positions of the FP64 values.
 template <typename T>
 struct Ell {
   int64_t n = 0;
@@ -44,7 +44,7 @@ struct Ell {
   int64_t padded = 0;
   int group = 1;
   int32_t* sptr = nullptr;  // [nslices + 1]
-  int32_t* col = nullptr;   // [padded]
+  int32_t* col = nullptr;   // [padded], null for offset-aligned slices
   T* val = nullptr;         // [padded]
   int32_t* doff = nullptr;  // [padded / 64] offsets of offset-aligned slices, or null
 };

@@ -162,11 +162,12 @@ __global__ __launch_bounds__(kWave) void k_slice_offsets(int64_t n, const int32_
 }
 
 // Offset-aligned fill: lane l of slice s (row r) puts, at step t, its entry of column r + offs[t]
-// (0 when the row has none); columns are clamped into [0, n).
+// (0 when the row has none), with the steps of a lane in pairs: step t at 64 (t - t % 2) + 2 l + t % 2
+// while t has a partner, an odd last step at 64 t + l.
 __global__ void k_ell_fill_aligned(int64_t n, int64_t nslices, const int32_t* __restrict__ ptr,
                                    const int32_t* __restrict__ col, const double* __restrict__ val,
                                    const int32_t* __restrict__ offs, const int32_t* __restrict__ sptr,
-                                   int32_t* __restrict__ ecol, double* __restrict__ eval, int32_t* __restrict__ doff) {
+                                   double* __restrict__ eval, int32_t* __restrict__ doff) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslices * kSlice) return;
   const int64_t s = t / kSlice;
@@ -179,15 +180,15 @@ __global__ void k_ell_fill_aligned(int64_t n, int64_t nslices, const int32_t* __
     p = ptr[r];
     pe = ptr[r + 1];
   }
+  const int paired = steps & ~1;
   for (int st = 0; st < steps; ++st) {
     const int o = offs[s * kSlice + st];
     const int64_t c = r + o;
     double v = 0.0;
     while (p < pe && col[p] < c) ++p;
     if (p < pe && col[p] == c) v = val[p++];
-    const int64_t q = base + (int64_t)st * kSlice + lane;
-    ecol[q] = (int32_t)(c < 0 ? 0 : (c > n - 1 ? n - 1 : c));
-    eval[q] = v;
+    const int dst = st < paired ? kSlice * (st & ~1) + 2 * lane + (st & 1) : kSlice * st + lane;
+    eval[base + dst] = v;
     if (lane == 0) doff[(base >> 6) + st] = o;
   }
 }
@@ -197,21 +198,6 @@ __global__ void k_round_f32(int64_t m, const double* __restrict__ a, float* __re
   if (i < m) b[i] = (float)a[i];
 }
 
-// FP32 copy of offset-aligned slices with each lane's steps in pairs: step t of lane l goes to
-// 64 (t - t % 2) + 2 l + t % 2 while t has a partner, an odd last step stays at 64 t + l.
-__global__ void k_round_f32_pairs(int64_t nslices, const int32_t* __restrict__ sptr, const double* __restrict__ a,
-                                  float* __restrict__ b) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = g >> 6;
-  const int lane = (int)(g & 63);
-  if (s >= nslices) return;
-  const int beg = sptr[s];
-  const int w = (sptr[s + 1] - beg) >> 6;
-  for (int t = 0; t < w; ++t) {
-    const int dst = t < (w & ~1) ? 64 * (t & ~1) + 2 * lane + (t & 1) : 64 * t + lane;
-    b[beg + dst] = (float)a[beg + 64 * t + lane];
-  }
-}
 
 // Box aggregates of edge e: row (i, j, k) of problem p -> coarse (i/e, j/e, k/e) of
 // problem p; an axis of extent 1 is not coarsened.  For e = 2, children[I*8 + c]
@@ -399,7 +385,6 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
   e.nslices = nslices;
   e.padded = acc;
   if (hipMalloc(&e.sptr, sizeof(int32_t) * (nslices + 1)) != hipSuccess ||
-      hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(acc, 1)) != hipSuccess ||
       hipMalloc(&e.val, sizeof(double) * std::max<int64_t>(acc, 1)) != hipSuccess ||
       hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(acc / kSlice, 1)) != hipSuccess) {
     free_ell(e);
@@ -411,7 +396,7 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
     rc = AMG_EHIP;
   if (rc == AMG_OK) {
     hipLaunchKernelGGL(k_ell_fill_aligned, dim3(grid_for(nslices * kSlice)), dim3(kBlock), 0, s, n, nslices, ptr,
-                       col, val, offs, e.sptr, e.col, e.val, e.doff);
+                       col, val, offs, e.sptr, e.val, e.doff);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
   }
   cleanup();
@@ -485,20 +470,18 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
   e.padded = a.padded;
   e.group = a.group;
   if (hipMalloc(&e.sptr, sizeof(int32_t) * (e.nslices + 1)) != hipSuccess) return AMG_ENOMEM;
-  if (hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;
   if (hipMalloc(&e.val, sizeof(float) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;
   AMGP_HIP(hipMemcpyAsync(e.sptr, a.sptr, sizeof(int32_t) * (e.nslices + 1), hipMemcpyDeviceToDevice, s));
-  AMGP_HIP(hipMemcpyAsync(e.col, a.col, sizeof(int32_t) * e.padded, hipMemcpyDeviceToDevice, s));
+  if (a.col) {
+    if (hipMalloc(&e.col, sizeof(int32_t) * std::max<int64_t>(e.padded, 1)) != hipSuccess) return AMG_ENOMEM;
+    AMGP_HIP(hipMemcpyAsync(e.col, a.col, sizeof(int32_t) * e.padded, hipMemcpyDeviceToDevice, s));
+  }
   if (a.doff) {
     if (hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(e.padded / kSlice, 1)) != hipSuccess) return AMG_ENOMEM;
     AMGP_HIP(hipMemcpyAsync(e.doff, a.doff, sizeof(int32_t) * (e.padded / kSlice), hipMemcpyDeviceToDevice, s));
   }
-  if (a.doff) {
-    hipLaunchKernelGGL(k_round_f32_pairs, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, e.nslices, e.sptr,
-                       a.val, e.val);
-  } else {
-    hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
-  }
+  // same positions in both precisions (the paired order of offset-aligned slices included)
+  hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
   AMGP_HIP(hipGetLastError());
   *out = e;
   return AMG_OK;

@@ -33,19 +33,23 @@ inline unsigned xcd_grid(int64_t n) {
 // neighbouring planes a row gathers were recently touched by the same XCD and
 // hit its L2 (measured: 40.9 vs 44.8 us per fused step at 128^3).  Larger
 // levels stream from HBM: there each XCD takes runs of kXcdChunk consecutive
-// blocks in turn, so that a block's neighbouring grid lines (the adjacent
-// blocks) are mostly on its own XCD, while the neighbouring planes, a multiple
-// of 8 runs away, still are (measured at 256^3: fetched bytes of the fused step
-// -11%, 381 vs 383 us; whole contiguous ranges per XCD: 450 us, since a
+// blocks in turn (blocks past the last whole round of 8 runs keep the launch
+// order), so that a block's neighbouring grid lines (the adjacent blocks) are
+// mostly on its own XCD and each XCD streams long contiguous stretches of the
+// matrix.  Measured on the fused step with runs of 8, 16, ..., 400 blocks:
+// 128 is the fastest on the 27-point level at 320^3 (1.63 ms; 8: 1.71,
+// 64: 1.67, 400: 1.73) and within 1.5% of the fastest on the 7-point level at
+// 256^3; whole contiguous ranges per XCD are slower on both (1.79 ms; a
 // plane's reuse is then too far away in time).  G is a multiple of 8 (xcd_grid).
 constexpr unsigned kRemapMaxBlocks = 16384;
-constexpr unsigned kXcdChunk = 8;
+constexpr unsigned kXcdChunk = 128;
 
 __device__ __forceinline__ int64_t logical_block() {
   if (gridDim.x > kRemapMaxBlocks) {
-    if (gridDim.x % (kXcd * kXcdChunk) != 0) return blockIdx.x;
+    constexpr unsigned span = kXcd * kXcdChunk;
+    if (blockIdx.x >= gridDim.x - gridDim.x % span) return blockIdx.x;
     const unsigned x = blockIdx.x % kXcd, q = blockIdx.x / kXcd;
-    return (int64_t)(q / kXcdChunk) * (kXcd * kXcdChunk) + x * kXcdChunk + q % kXcdChunk;
+    return (int64_t)(q / kXcdChunk) * span + x * kXcdChunk + q % kXcdChunk;
   }
   const unsigned per = gridDim.x / kXcd;
   return (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
@@ -73,10 +77,16 @@ __device__ __forceinline__ void st(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
-// FP32 offset-aligned slices keep each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit
-// at 128 q + 2 l and 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so one 8-byte
-// load per lane serves two steps and a wavefront load is 512 contiguous bytes, as in FP64.
+// Offset-aligned slices keep each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit at
+// 128 q + 2 l and 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so one load per
+// lane serves two steps: 16 bytes in FP64 (a wavefront load is 1 KB contiguous), 8 in FP32.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ f64x2 ld2(const double* p) {
+  const f64x2* q = reinterpret_cast<const f64x2*>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q); else return *q;
+}
 template <bool NT>
 __device__ __forceinline__ f32x2 ld2(const float* p) {
   const f32x2* q = reinterpret_cast<const f32x2*>(p);
@@ -101,6 +111,57 @@ __device__ __forceinline__ float aligned_sum_f32(const float* __restrict__ val, 
     acc += p.y * g(c1);
   }
   if (t < w) acc += ld<NT>(v + 64 * t + lane) * g(min(max(r + off[t], 0), last));
+  return acc;
+}
+
+// The FP64 form: the same sum in ascending t, with the requests issued in batches of
+// kAlignedBatch steps (three 16-byte loads per lane) and the next batch's values requested
+// before this batch's products are added, so that each wavefront keeps a batch of matrix loads
+// in flight while it waits for its gathers.  Measured on the fused step: 27-point level at 320^3
+// 1.63 ms (one pair per iteration: 1.71; one unpaired step per iteration, unrolled by 2: 1.85),
+// 7-point level at 256^3 0.296 ms (batches of 8: 0.305; unpaired: 0.319).
+constexpr int kAlignedBatch = 6;
+
+// Batched = false: one pair per iteration (rows of a wavefront in different slices, where the
+// batches would diverge).
+template <bool NT, typename Gf, bool Batched = true>
+__device__ __forceinline__ double aligned_sum_f64(const double* __restrict__ val, int beg, int end, int lane,
+                                                  const int32_t* __restrict__ off, int r, int last, Gf g) {
+  constexpr int B = kAlignedBatch, H = kAlignedBatch / 2;
+  const int w = (end - beg) >> 6;
+  const int wp = w & ~1;
+  const int nb = Batched ? wp / B : 0;
+  const double* v = val + beg + 2 * lane;  // pair u of batch q at v + 64 (q B) + 128 u
+  double acc = 0.0;
+  int t = 0;
+  f64x2 nxt[H];
+  if (nb > 0) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) nxt[u] = ld2<NT>(v + 128 * u);
+  }
+  for (int q = 0; q < nb; ++q, t += B) {
+    f64x2 cur[H];
+    double gv[B];
+#pragma unroll
+    for (int u = 0; u < H; ++u) cur[u] = nxt[u];
+#pragma unroll
+    for (int u = 0; u < B; ++u) gv[u] = g(min(max(r + off[t + u], 0), last));
+    if (q + 1 < nb) {
+#pragma unroll
+      for (int u = 0; u < H; ++u) nxt[u] = ld2<NT>(v + 64 * (t + B) + 128 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      acc += cur[u].x * gv[2 * u];
+      acc += cur[u].y * gv[2 * u + 1];
+    }
+  }
+  for (; t < wp; t += 2) {
+    const f64x2 p = ld2<NT>(v + 64 * t);
+    acc += p.x * g(min(max(r + off[t], 0), last));
+    acc += p.y * g(min(max(r + off[t + 1], 0), last));
+  }
+  if (t < w) acc += ld<NT>(val + beg + 64 * t + lane) * g(min(max(r + off[t], 0), last));
   return acc;
 }
 
@@ -136,13 +197,9 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
     const int r = (int)row;
     if constexpr (std::is_same_v<T, float>) {
       return aligned_sum_f32<NT>(A.val, beg, end, lane, off, r, A.last, [&](int c) { return x[c]; });
+    } else {
+      return aligned_sum_f64<NT>(A.val, beg, end, lane, off, r, A.last, [&](int c) { return x[c]; });
     }
-#pragma unroll 2
-    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
-      const int c = min(max(r + off[t], 0), A.last);
-      acc += ld<NT>(A.val + p) * x[c];
-    }
-    return acc;
   }
 #pragma unroll 4
   for (int p = beg + lane; p < end; p += kSlice) {
@@ -291,12 +348,9 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
         return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
       });
     } else {
-#pragma unroll 2
-      for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
-        const int j = min(max((int)i + off[t], 0), A.last);
-        const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-        ag += ld<NT>(A.val + p) * g1j;
-      }
+      ag = aligned_sum_f64<NT>(A.val, beg, end, lane, off, (int)i, A.last, [&](int j) {
+        return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
+      });
     }
   } else {
 #pragma unroll 4
@@ -371,13 +425,10 @@ __device__ __forceinline__ T ell_dot_prol(EllView<T> A, int64_t row, const T* __
     if constexpr (std::is_same_v<T, float>) {
       return aligned_sum_f32<NT>(A.val, beg, end, lane, off, r, A.last,
                                  [&](int c) { return x[c] + pr.xc[pr.agg[c]]; });
+    } else {
+      return aligned_sum_f64<NT>(A.val, beg, end, lane, off, r, A.last,
+                                 [&](int c) { return x[c] + pr.xc[pr.agg[c]]; });
     }
-#pragma unroll 2
-    for (int p = beg + lane, t = 0; p < end; p += kSlice, ++t) {
-      const int c = min(max(r + off[t], 0), A.last);
-      acc += ld<NT>(A.val + p) * (x[c] + pr.xc[pr.agg[c]]);
-    }
-    return acc;
   }
 #pragma unroll 4
   for (int p = beg + lane; p < end; p += kSlice) {
@@ -459,13 +510,10 @@ __device__ __forceinline__ T ell_dot_any(EllView<T> A, int row, const T* __restr
     const int32_t* off = A.doff + (beg >> 6);
     if constexpr (std::is_same_v<T, float>) {
       return aligned_sum_f32<NT>(A.val, beg, end, row & 63, off, row, A.last, [&](int c) { return x[c]; });
+    } else {
+      auto g = [&](int c) { return x[c]; };
+      return aligned_sum_f64<NT, decltype(g), false>(A.val, beg, end, row & 63, off, row, A.last, g);
     }
-#pragma unroll 2
-    for (int p = beg + (row & 63), t = 0; p < end; p += kSlice, ++t) {
-      const int c = min(max(row + off[t], 0), A.last);
-      acc += ld<NT>(A.val + p) * x[c];
-    }
-    return acc;
   }
 #pragma unroll 4
   for (int p = beg + (row & 63); p < end; p += kSlice) acc += ld<NT>(A.val + p) * x[ld<NT>(A.col + p)];
@@ -599,11 +647,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     double acc = 0.0;
     if (A.doff) {
       const int32_t* off = A.doff + (beg >> 6);
-#pragma unroll 2
-      for (int p = beg + (int)(i & 63), t = 0; p < end; p += kSlice, ++t) {
-        const int j = min(max((int)i + off[t], 0), A.last);
-        acc += ld<kStreamVal>(A.val + p) * ((double)z[j] + beta * pold[j]);
-      }
+      acc = aligned_sum_f64<kStreamVal>(A.val, beg, end, (int)(i & 63), off, (int)i, A.last,
+                                        [&](int j) { return (double)z[j] + beta * pold[j]; });
     } else {
 #pragma unroll 4
       for (int p = beg + (int)(i & 63); p < end; p += kSlice) {

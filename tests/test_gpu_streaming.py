@@ -1,16 +1,17 @@
 """Full-vector parity of the streaming kernels (levels above 16384 blocks of 256 rows).
 
 Levels of more than 4.2M rows take kernels with nontemporal loads and stores
-and, when the block count is a multiple of 64, a block order that hands runs
-of 8 consecutive blocks to each XCD.  Every full-size workload runs its fine
-level on these kernels.  Here they are compared with the oracle on every
-entry (NaN-prefilled outputs, the element-wise and norm-wise bound of
-`relerr`):
-* 7-point 128 x 128 x 257 (4,210,688 rows, 16448 blocks: remapped), all four
-  kinds at degrees 1..6 from x = 0, degree 3 from x != 0, and V-cycles;
-* 7-point 256^3 (16,777,216 rows, 65536 blocks: remapped), the optimal kinds
-  at degrees 1..6, the other two at 1, 4 and 6, and one V-cycle;
-* 27-point Q1 164^3 (4,410,944 rows, 17232 blocks: streaming in launch order);
+and a block order that hands runs of 128 consecutive blocks to each XCD in
+turn; the blocks past the last whole round of 8 runs (1024 blocks) keep the
+launch order.  Every full-size workload runs its fine level on these kernels.
+Here they are compared with the oracle on every entry (NaN-prefilled outputs,
+the element-wise and norm-wise bound of `relerr`):
+* 7-point 128 x 128 x 257 (4,210,688 rows, 16448 blocks: 16 rounds and a tail
+  of 64 blocks), all four kinds at degrees 1..6 from x = 0, degree 3 from
+  x != 0, and V-cycles;
+* 7-point 256^3 (16,777,216 rows, 65536 blocks: whole rounds only), the
+  optimal kinds at degrees 1..6, the other two at 1, 4 and 6, and one V-cycle;
+* 27-point Q1 164^3 (4,410,944 rows, 17232 blocks: a tail of 848 blocks);
 * the differentiable V-cycle and the training loss on 20 stacked 64^3
   diffusion problems (5,242,880 rows, 20480 blocks) at degree 6, against the
   oracle per problem and the complex-step derivative on sampled weights.
@@ -35,6 +36,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 STREAM_MIN_BLOCKS = 16384
+XCD_ROUND = 8 * 128  # blocks per round of XCD runs on streaming levels
 
 
 def _log(msg):
@@ -58,7 +60,7 @@ class _Problem:
 def p4m():
     torch_cuda()
     A = W.poisson3d_7pt(128, 128, 257)
-    assert _blocks(A.n) > STREAM_MIN_BLOCKS and _blocks(A.n) % 64 == 0
+    assert _blocks(A.n) > STREAM_MIN_BLOCKS and _blocks(A.n) % XCD_ROUND == 64
     return _Problem(A, 301)
 
 
@@ -138,11 +140,11 @@ def test_streaming_vcycle_256(p256):
     assert e <= TOL
 
 
-def test_streaming_27pt_unremapped():
+def test_streaming_27pt_tail_blocks():
     torch = torch_cuda()
     import paper_2407_09848_amd as amg
     A = W.q1_27pt(164)
-    assert _blocks(A.n) > STREAM_MIN_BLOCKS and ((_blocks(A.n) + 7) // 8 * 8) % 64 != 0
+    assert _blocks(A.n) > STREAM_MIN_BLOCKS and ((_blocks(A.n) + 7) // 8 * 8) % XCD_ROUND == 848
     pr = _Problem(A, 303)
     with hierarchy(A) as h:
         padded, lanes, aligned = amg.amg_level_layout(h, 0)
@@ -166,7 +168,7 @@ def stack20():
     sig = W.config4_sigmas(P_)
     mats = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((n,) * 3, 8.0, 400 + p))) for p in range(P_)]
     big = W.stack_block_diagonal(mats)
-    assert _blocks(big.n) > STREAM_MIN_BLOCKS and _blocks(big.n) % 64 == 0
+    assert _blocks(big.n) > STREAM_MIN_BLOCKS and _blocks(big.n) % XCD_ROUND == 0
     Hs = [OA.build_hierarchy(m.to_scipy(), m.grid) for m in mats]
     rng = np.random.default_rng(31)
     base = np.array(P.optimal_beta(6)[0])
