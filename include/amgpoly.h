@@ -297,6 +297,16 @@ int mlp_bwd(const float* d_params, const float* d_x, int batch, const float* d_c
 int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, int step, float lr, float b1,
              float b2, float eps, void* stream);
 
+/* mlp_bwd for callers that cannot allocate device memory (code under HIP graph capture, serving
+ * or training loops that forbid allocation): the same gradients, bitwise, with no workspace
+ * argument.  Its scratch (2 * batch * 64 floats) is a static array inside the library, one per
+ * GPU (128 KB, held until the process ends); the call allocates and frees nothing.  Limit:
+ * 1 <= batch <= 256 (AMG_ECAPACITY above, AMG_EINVAL for batch < 1 or a null pointer).  Calls
+ * on one GPU share its array, so calls that overlap in time on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller.  Asynchronous on `stream`. */
+int mlp_bwd_noalloc(const float* d_params, const float* d_x, int batch, const float* d_cache, const float* d_gy,
+                    float* d_gparams, void* stream);
+
 /* d_valid[q] = 1 when the weighted 4th-kind polynomial of row q of d_beta (count rows of
  * `degree` weights) stays inside Pi_k (eq. polspace): |p(x)| < 1 at x = m/ngrid, m = 1..ngrid
  * (p(0) = 1 holds for any weights); else 0.  Used to fall back to the tabulated weights. */

@@ -20,7 +20,8 @@ __all__ = [
     "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
     "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
-    "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_adam",
+    "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_bwd_noalloc",
+    "mlp_adam",
     "amg_beta_valid", "amg_learned_beta", "amg_learned_beta_grad", "amg_hbm_read", "amg_hbm_copy",
     "AMG_HBM_PARTIALS", "VCycleFunction",
     "AMG_OK", "AMG_NOT_CONVERGED", "AMG_EINVAL", "AMG_ENOTSPD", "AMG_ENOMEM", "AMG_EHIP",
@@ -80,6 +81,7 @@ _SIGS = {
     "mlp_num_params": (_I, []),
     "mlp_fwd": (_I, [_P, _P, _I, _P, _P, _P]),
     "mlp_bwd": (_I, [_P, _P, _I, _P, _P, _P, _P, _P]),
+    "mlp_bwd_noalloc": (_I, [_P, _P, _I, _P, _P, _P, _P]),
     "mlp_adam": (_I, [_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "amg_beta_valid": (_I, [_P, _I, _I, _I, _P, _P]),
     "amg_learned_beta": (_I, [_P, _I, _P, _I, _P, _P, _P]),
@@ -352,6 +354,15 @@ def mlp_bwd(params, x, cache, gy, gparams, work):
     return _check(lib().mlp_bwd(_ptr(params, torch.float32), _ptr(x, torch.float32), B, _ptr(cache, torch.float32),
                                 _ptr(gy, torch.float32), _ptr(gparams, torch.float32), _ptr(work, torch.float32),
                                 _stream()), "mlp_bwd")
+
+
+def mlp_bwd_noalloc(params, x, cache, gy, gparams):
+    """mlp_bwd with the library's own static scratch (no workspace argument, batch <= 256)."""
+    import torch
+    B = x.shape[0]
+    return _check(lib().mlp_bwd_noalloc(_ptr(params, torch.float32), _ptr(x, torch.float32), B,
+                                        _ptr(cache, torch.float32), _ptr(gy, torch.float32),
+                                        _ptr(gparams, torch.float32), _stream()), "mlp_bwd_noalloc")
 
 
 def mlp_adam(params, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

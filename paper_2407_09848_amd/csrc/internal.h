@@ -291,6 +291,9 @@ int launch_restrict_sum(hipStream_t s, int64_t nc, const int32_t* children, cons
 int launch_mlp_fwd(hipStream_t s, int B, const float* W, const float* X, float* Y, float* cache);
 int launch_mlp_bwd(hipStream_t s, int B, const float* W, const float* X, const float* cache, const float* dY,
                    float* G, float* work);
+// mlp_bwd with its scratch in the library's static per-device array (batch <= 256)
+int launch_mlp_bwd_noalloc(hipStream_t s, int B, const float* W, const float* X, const float* cache,
+                           const float* dY, float* G);
 int launch_adam(hipStream_t s, int n, float* W, const float* G, float* m, float* v, float lr, float b1, float b2,
                 float eps, float c1, float c2);
 int launch_beta_valid(hipStream_t s, int count, int k, const double* beta, int ngrid, int* valid);

@@ -6,6 +6,8 @@
 // Every reduction has a fixed association order (one block per problem
 // segment, then a fixed-order sum of the block partials), so results are
 // bitwise reproducible.
+#include <mutex>
+
 #include "internal.h"
 
 namespace amgp {
@@ -351,6 +353,46 @@ int launch_mlp_bwd(hipStream_t s, int B, const float* W, const float* X, const f
                    float* G, float* work) {
   hipLaunchKernelGGL(k_mlp_bwd, dim3(1), dim3(256), 0, s, B, W, X, cache, dY, G, work);
   return LAUNCH_OK();
+}
+
+// ---------------------------------------------------------------------------
+// mlp_bwd without a caller-supplied workspace: the backward's scratch (dz2, dz1 of up to
+// kMlpMaxBatch rows, 128 KB) is this file-scope device array, one copy per GPU, held until
+// the process ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): each device's address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and is kept here.  Every call on a GPU
+// shares that GPU's array, so calls that overlap on one GPU (different streams) race; the
+// kernel writes every scratch entry it reads, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr int kMlpMaxBatch = 256;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) float scratch[2 * kMlpMaxBatch * NH];
+
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on each device).
+static int scratch_address(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return AMG_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return AMG_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return AMG_EHIP;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return AMG_OK;
+}
+
+int launch_mlp_bwd_noalloc(hipStream_t s, int B, const float* W, const float* X, const float* cache,
+                           const float* dY, float* G) {
+  if (B > kMlpMaxBatch) return AMG_ECAPACITY;
+  float* work = nullptr;
+  const int rc = scratch_address(&work);
+  if (rc != AMG_OK) return rc;
+  return launch_mlp_bwd(s, B, W, X, cache, dY, G, work);
 }
 
 int launch_adam(hipStream_t s, int n, float* W, const float* G, float* m, float* v, float lr, float b1, float b2,

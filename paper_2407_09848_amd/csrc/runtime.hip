@@ -1233,6 +1233,12 @@ int mlp_bwd(const float* d_params, const float* d_x, int batch, const float* d_c
   return amgp::launch_mlp_bwd((hipStream_t)stream, batch, d_params, d_x, d_cache, d_gy, d_gparams, d_work);
 }
 
+int mlp_bwd_noalloc(const float* d_params, const float* d_x, int batch, const float* d_cache, const float* d_gy,
+                    float* d_gparams, void* stream) {
+  if (!d_params || !d_x || !d_cache || !d_gy || !d_gparams || batch < 1) return AMG_EINVAL;
+  return amgp::launch_mlp_bwd_noalloc((hipStream_t)stream, batch, d_params, d_x, d_cache, d_gy, d_gparams);
+}
+
 int mlp_adam(float* d_params, const float* d_g, float* d_m, float* d_v, int n, int step, float lr, float b1, float b2,
              float eps, void* stream) {
   if (!d_params || !d_g || !d_m || !d_v || n < 1 || step < 1) return AMG_EINVAL;
