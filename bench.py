@@ -363,8 +363,10 @@ def main():
     t0 = time.perf_counter()
     A, b, _ = W.config_problem(5, size=args.size)
     assembly_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
     torch.cuda.synchronize()
+    upload_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     h = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64)
     torch.cuda.synchronize()
@@ -491,7 +493,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"q1_27pt_{args.size}^3_amg_pcg_to_1e-8",
                    "smoother": KIND_NAMES[args.kind], "degree": args.degree, "n": int(n0), "nnz": int(nnz0),
-                   "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2),
+                   "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2), "upload_s": round(upload_s, 3),
                    "setup_s": round(setup_s, 3)},
         "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
         "learned": learned_info, "diffusion_256": c3,
