@@ -56,11 +56,18 @@ def matrix_bytes(amg, h, level, w):
 
 
 def level_table(amg, h, w):
-    """[(n, M, lanes)] for every level of handle h, with values of w bytes."""
+    """[(n, M, lanes, R)] for every level of handle h, with values of w bytes; R is the bytes of the
+    restriction product's slices (0 when the level restricts its residual instead)."""
     out = []
-    for l in range(amg.amg_num_levels(h)):
+    L = amg.amg_num_levels(h)
+    for l in range(L):
         n, _ = amg.amg_level_info(h, l)
-        out.append((n, matrix_bytes(amg, h, l, w), amg.amg_level_layout(h, l)[1]))
+        R = 0
+        if l < L - 1:
+            form, stored = amg.amg_level_transfer(h, l)
+            if form == amg.AMG_TRANSFER_PRODUCT:
+                R = stored * w + 4 * (stored // 64)
+        out.append((n, matrix_bytes(amg, h, l, w), amg.amg_level_layout(h, l)[1], R))
     return out
 
 
@@ -90,10 +97,12 @@ def smooth_bytes(n, M, w, kind, k, from_zero, nc=0, prol=0):
 
 def vcycle_bytes(levels, w, kind, k, nbatch=1):
     tot = 0
-    for l, (n, M, lanes) in enumerate(levels[:-1]):
+    for l, (n, M, lanes, R) in enumerate(levels[:-1]):
         nc = levels[l + 1][0]
         tot += smooth_bytes(n, M, w, kind, k, True)
-        if n > FUSED_PROLONG_MAX_ROWS:  # residual, then restriction over 8 children
+        if R:  # b_c = P^T b - R x: R, b and x once, the children, b_c
+            tot += R + 2 * w * n + 32 * nc + w * nc
+        elif n > FUSED_PROLONG_MAX_ROWS:  # residual, then restriction over 8 children
             tot += M + 3 * w * n + w * n + 32 * nc + w * nc
         else:
             tot += M + 2 * w * n + 32 * nc + w * nc

@@ -151,6 +151,19 @@ int amg_level_info(const amg_handle* h, int level, int64_t* h_n, int64_t* h_nnz)
  * offset, no column indices read), else 0. */
 int amg_level_layout(const amg_handle* h, int level, int64_t* h_padded, int* h_lanes, int* h_aligned);
 
+/* How the restriction from level l to level l + 1 is computed (host outputs, any may be NULL;
+ * AMG_EINVAL on the coarsest level): *h_form = AMG_TRANSFER_RESIDUAL (2x2x2 boxes: the fine
+ * residual b - A x, then the sum over each aggregate's rows), AMG_TRANSFER_PRODUCT (2x2x2 boxes:
+ * b_c = P^T b - R x with the restriction product R = P^T A, the Galerkin construction's first
+ * factor of Section 2, stored in offset-aligned slices with offsets taken against each
+ * aggregate's first row; no fine residual is formed) or AMG_TRANSFER_EXPLICIT (smoothed or
+ * other prolongators: P^T as a sparse matrix).  *h_stored: stored entries of R or P^T
+ * including padding, 0 for the residual form. */
+#define AMG_TRANSFER_RESIDUAL 0
+#define AMG_TRANSFER_PRODUCT 1
+#define AMG_TRANSFER_EXPLICIT 2
+int amg_level_transfer(const amg_handle* h, int level, int* h_form, int64_t* h_stored);
+
 /* Copy level l's Galerkin operator (CSR, sorted columns) and its l1 inverse
  * diagonal 1/M_i into caller buffers: d_row_ptr[n+1], d_col[nnz], d_val[nnz],
  * d_minv[n] (float64).  Any pointer may be NULL to skip it.  Asynchronous. */

@@ -13,9 +13,11 @@ AMG_FP64, AMG_FP32 = 0, 1
 AMG_AGG_BOX, AMG_AGG_MATCHING, AMG_AGG_VBM = 0, 1, 2
 AMG_MAX_DEGREE = 12
 AMG_HBM_PARTIALS = 16384
+AMG_TRANSFER_RESIDUAL, AMG_TRANSFER_PRODUCT, AMG_TRANSFER_EXPLICIT = 0, 1, 2
 
 __all__ = [
     "LIB_PATH", "AmgError", "lib", "amg_setup", "amg_destroy", "amg_num_levels", "amg_level_info", "amg_level_layout",
+    "amg_level_transfer", "AMG_TRANSFER_RESIDUAL", "AMG_TRANSFER_PRODUCT", "AMG_TRANSFER_EXPLICIT",
     "amg_level_export", "amg_level_aggregates", "amg_default_beta", "amg_default_astar", "amg_set_beta",
     "amg_reset_beta",
     "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
@@ -58,6 +60,7 @@ _SIGS = {
     "amg_level_export": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "amg_level_aggregates": (_I, [_P, _I, _P, _P]),
     "amg_level_layout": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "amg_level_transfer": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I64)]),
     "amg_default_beta": (_I, [_I, ctypes.POINTER(_D)]),
     "amg_default_astar": (_I, [_I, ctypes.POINTER(_D)]),
     "amg_set_beta": (_I, [_P, _I, _I, ctypes.POINTER(_D)]),
@@ -173,6 +176,13 @@ def amg_level_layout(h, level):
     _check(lib().amg_level_layout(h, level, ctypes.byref(padded), ctypes.byref(lanes), ctypes.byref(aligned)),
            "amg_level_layout")
     return padded.value, lanes.value, bool(aligned.value)
+
+
+def amg_level_transfer(h, level):
+    """(form, stored entries) of the restriction from level l (AMG_TRANSFER_*)."""
+    form, stored = _I(), _I64()
+    _check(lib().amg_level_transfer(h, level, ctypes.byref(form), ctypes.byref(stored)), "amg_level_transfer")
+    return form.value, stored.value
 
 
 def amg_level_export(h, level):

@@ -47,6 +47,11 @@ struct Ell {
   int32_t* col = nullptr;   // [padded], null for offset-aligned slices
   T* val = nullptr;         // [padded]
   int32_t* doff = nullptr;  // [padded / 64] offsets of offset-aligned slices, or null
+  int64_t ncols = 0;        // columns (0: square, n)
+  // offset-aligned slices of a rectangular matrix are aligned on an anchor column per row
+  // instead of the row itself: column = anchor[r * astride] + offset (null: the row)
+  const int32_t* anchor = nullptr;
+  int astride = 1;
 };
 
 // Per-problem smoother weights for stacked problems: the weight of row i is
@@ -72,12 +77,12 @@ struct EllView {
   const int32_t* __restrict__ col;
   const T* __restrict__ val;
   const int32_t* __restrict__ doff;
-  int32_t last;  // n - 1, the clamp of offset-aligned columns
+  int32_t last;  // columns - 1, the clamp of offset-aligned columns
 };
 
 template <typename T>
 inline EllView<T> view(const Ell<T>& e) {
-  return EllView<T>{e.sptr, e.col, e.val, e.doff, (int32_t)(e.n - 1)};
+  return EllView<T>{e.sptr, e.col, e.val, e.doff, (int32_t)((e.ncols > 0 ? e.ncols : e.n) - 1)};
 }
 
 // Work vectors of one level in one precision.
@@ -111,6 +116,10 @@ struct Level {
   bool general = false;
   Ell<double> P64, PT64;
   Ell<float> P32, PT32;
+  // 2x2x2 boxes: the restriction product R = P^T A (nc x n) in slices aligned on each aggregate's
+  // first row, so that b_c = P^T b - R x needs no fine residual (empty when it does not fit)
+  Ell<double> R64;
+  Ell<float> R32;
 };
 
 // Device CSR matrix (m x ncols) used by the setup's general sparse products.
@@ -241,6 +250,9 @@ template <typename T>
 int launch_jacobi_zero(hipStream_t s, int64_t n, const T* minv, const T* b, T* x);
 // transfers
 // b_c = P^T (b - A x); tmp (n entries) is scratch (one row per lane matrices do not touch it)
+// b_c = P^T b - R x with R = P^T A in anchor-aligned slices (2x2x2 boxes)
+template <typename T>
+int launch_restrict_product(hipStream_t s, const Ell<T>& R, const int32_t* children, const T* b, const T* x, T* bc);
 template <typename T>
 int launch_restrict(hipStream_t s, const Ell<T>& A, int64_t nc, const int32_t* children, const T* b,
                     const T* x, T* tmp, T* bc);
@@ -323,6 +335,12 @@ int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* 
 int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
                 Ell<double>* out, int64_t ncols = -1, int group = 1);
 int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out);
+// offset-aligned slices (one row per lane) with the offsets taken against anchor[r * astride]
+// (null: the row r) and columns clamped into [0, ncols) (-1: n); AMG_EINVAL when a slice has more
+// than 64 offsets or (unless any_size) the layout is more than 10% larger than the packed one
+int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
+                      Ell<double>* out, const int32_t* anchor = nullptr, int astride = 1, int64_t ncols = -1,
+                      bool any_size = false);
 // box aggregates of edge e; children (2x2x2 boxes only) may be null
 int launch_aggregates(hipStream_t s, int nx, int ny, int nz, int nbatch, int e, int32_t* agg, int32_t* children,
                       int* cnx, int* cny, int* cnz);

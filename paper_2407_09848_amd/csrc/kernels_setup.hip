@@ -101,13 +101,15 @@ __global__ void k_ell_fill(int64_t n, int64_t ncols, int64_t nslices, int G, con
   }
 }
 
-// Distinct column offsets (col - row) of every 64-row slice, sorted: offs[s * 64 + t], count
-// width[s] (-1 when there are more than 64).  One wavefront per slice, an LDS hash set.
+// Distinct column offsets (col - row, or col - anchor[row * astride]) of every 64-row slice,
+// sorted: offs[s * 64 + t], count width[s] (-1 when there are more than 64).  One wavefront per
+// slice, an LDS hash set.
 constexpr int kOffHash = 256;
 constexpr int kOffEmpty = INT_MIN;
 
 __global__ __launch_bounds__(kWave) void k_slice_offsets(int64_t n, const int32_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ col, int32_t* __restrict__ offs,
+                                                         const int32_t* __restrict__ col, const int32_t* anchor,
+                                                         int astride, int32_t* __restrict__ offs,
                                                          int32_t* __restrict__ width) {
   __shared__ int set[kOffHash];
   __shared__ int list[kOffHash];
@@ -119,8 +121,9 @@ __global__ __launch_bounds__(kWave) void k_slice_offsets(int64_t n, const int32_
   __syncthreads();
   const int64_t r = s * kSlice + lane;
   if (r < n) {
+    const int base = anchor ? anchor[r * astride] : (int)r;
     for (int p = ptr[r]; p < ptr[r + 1]; ++p) {
-      const int o = col[p] - (int)r;
+      const int o = col[p] - base;
       unsigned h = ((unsigned)o * 2654435761u) & (kOffHash - 1);
       for (int probe = 0; probe < kOffHash; ++probe) {
         const int old = atomicCAS(&set[h], kOffEmpty, o);
@@ -161,13 +164,14 @@ __global__ __launch_bounds__(kWave) void k_slice_offsets(int64_t n, const int32_
   if (lane == 0) width[s] = c;
 }
 
-// Offset-aligned fill: lane l of slice s (row r) puts, at step t, its entry of column r + offs[t]
-// (0 when the row has none), with the steps of a lane in pairs: step t at 64 (t - t % 2) + 2 l + t % 2
-// while t has a partner, an odd last step at 64 t + l.
+// Offset-aligned fill: lane l of slice s (row r, anchor a = r or anchor[r * astride]) puts, at
+// step t, its entry of column a + offs[t] (0 when the row has none), with the steps of a lane in
+// pairs: step t at 64 (t - t % 2) + 2 l + t % 2 while t has a partner, an odd last step at 64 t + l.
 __global__ void k_ell_fill_aligned(int64_t n, int64_t nslices, const int32_t* __restrict__ ptr,
                                    const int32_t* __restrict__ col, const double* __restrict__ val,
-                                   const int32_t* __restrict__ offs, const int32_t* __restrict__ sptr,
-                                   double* __restrict__ eval, int32_t* __restrict__ doff) {
+                                   const int32_t* anchor, int astride, const int32_t* __restrict__ offs,
+                                   const int32_t* __restrict__ sptr, double* __restrict__ eval,
+                                   int32_t* __restrict__ doff) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslices * kSlice) return;
   const int64_t s = t / kSlice;
@@ -176,14 +180,16 @@ __global__ void k_ell_fill_aligned(int64_t n, int64_t nslices, const int32_t* __
   const int base = sptr[s];
   const int steps = (sptr[s + 1] - base) / kSlice;
   int p = 0, pe = 0;
+  int64_t a = r;
   if (r < n) {
     p = ptr[r];
     pe = ptr[r + 1];
+    if (anchor) a = anchor[r * astride];
   }
   const int paired = steps & ~1;
   for (int st = 0; st < steps; ++st) {
     const int o = offs[s * kSlice + st];
-    const int64_t c = r + o;
+    const int64_t c = a + o;
     double v = 0.0;
     while (p < pe && col[p] < c) ++p;
     if (p < pe && col[p] == c) v = val[p++];
@@ -336,7 +342,7 @@ int launch_l1_diag(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* 
 // Offset-aligned sliced ELL (one row per lane) when every slice has at most 64 distinct column
 // offsets and the layout is at most 10% larger than the packed one; AMG_EINVAL otherwise.
 int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col, const double* val,
-                      Ell<double>* out) {
+                      Ell<double>* out, const int32_t* anchor, int astride, int64_t ncols, bool any_size) {
   const int64_t nslices = (n + kSlice - 1) / kSlice;
   int32_t *offs = nullptr, *wd = nullptr, *lw = nullptr;
   auto cleanup = [&]() {
@@ -350,7 +356,8 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
     cleanup();
     return AMG_ENOMEM;
   }
-  hipLaunchKernelGGL(k_slice_offsets, dim3((unsigned)nslices), dim3(kWave), 0, s, n, ptr, col, offs, wd);
+  hipLaunchKernelGGL(k_slice_offsets, dim3((unsigned)nslices), dim3(kWave), 0, s, n, ptr, col, anchor, astride, offs,
+                     wd);
   hipLaunchKernelGGL(k_slice_width, dim3(grid_for(nslices)), dim3(kBlock), 0, s, n, nslices, kSlice, ptr, lw);
   std::vector<int32_t> w(nslices), lwh(nslices);
   if (hipMemcpyAsync(w.data(), wd, sizeof(int32_t) * nslices, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -368,7 +375,7 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
     aligned += (int64_t)w[i] * kSlice;
     packed += (int64_t)lwh[i] * kSlice;
   }
-  if (aligned > packed + packed / 10 || aligned >= (int64_t)INT32_MAX) {
+  if ((!any_size && aligned > packed + packed / 10) || aligned >= (int64_t)INT32_MAX) {
     cleanup();
     return AMG_EINVAL;
   }
@@ -381,6 +388,9 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
   sp[nslices] = (int32_t)acc;
   Ell<double> e;
   e.n = n;
+  e.ncols = ncols < 0 ? n : ncols;
+  e.anchor = anchor;
+  e.astride = astride;
   e.group = 1;
   e.nslices = nslices;
   e.padded = acc;
@@ -396,7 +406,7 @@ int build_ell_aligned(hipStream_t s, int64_t n, const int32_t* ptr, const int32_
     rc = AMG_EHIP;
   if (rc == AMG_OK) {
     hipLaunchKernelGGL(k_ell_fill_aligned, dim3(grid_for(nslices * kSlice)), dim3(kBlock), 0, s, n, nslices, ptr,
-                       col, val, offs, e.sptr, e.val, e.doff);
+                       col, val, anchor, astride, offs, e.sptr, e.val, e.doff);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = AMG_EHIP;
   }
   cleanup();
@@ -466,6 +476,9 @@ int build_ell64(hipStream_t s, int64_t n, const int32_t* ptr, const int32_t* col
 int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
   Ell<float> e;
   e.n = a.n;
+  e.ncols = a.ncols;
+  e.anchor = a.anchor;
+  e.astride = a.astride;
   e.nslices = a.nslices;
   e.padded = a.padded;
   e.group = a.group;

@@ -21,6 +21,7 @@ struct Prec<double> {
   static const Ell<double>& A(const Level& l) { return l.A64; }
   static const Ell<double>& P(const Level& l) { return l.P64; }
   static const Ell<double>& PT(const Level& l) { return l.PT64; }
+  static const Ell<double>& R(const Level& l) { return l.R64; }
   static Vecs<double>& v(Level& l) { return l.v64; }
 };
 template <>
@@ -28,6 +29,7 @@ struct Prec<float> {
   static const Ell<float>& A(const Level& l) { return l.A32; }
   static const Ell<float>& P(const Level& l) { return l.P32; }
   static const Ell<float>& PT(const Level& l) { return l.PT32; }
+  static const Ell<float>& R(const Level& l) { return l.R32; }
   static Vecs<float>& v(Level& l) { return l.v32; }
 };
 
@@ -84,6 +86,8 @@ void release(Handle* h) {
     free_ell(L.PT64);
     free_ell(L.P32);
     free_ell(L.PT32);
+    free_ell(L.R64);
+    free_ell(L.R32);
   }
   hipFree(h->ainv);
   hipFree(h->cpart);
@@ -248,6 +252,7 @@ int coarse(Handle* h, const T* b, T* x, hipStream_t s) {
 template <typename T>
 int restrict_res(Handle* h, int l, const T* b, const T* x, T* tmp, T* bc, hipStream_t s) {
   Level& L = h->lv[l];
+  if (!L.general && Prec<T>::R(L).val) return launch_restrict_product<T>(s, Prec<T>::R(L), L.children, b, x, bc);
   if (!L.general) return launch_restrict<T>(s, Prec<T>::A(L), L.nc, L.children, b, x, tmp, bc);
   AMGP_TRY(launch_residual<T>(s, Prec<T>::A(L), b, x, tmp));
   return launch_spmv<T>(s, Prec<T>::PT(L), tmp, bc);
@@ -601,6 +606,21 @@ int general_level(Handle* h, hipStream_t s, Level& L, Level* C, Csr* Phat) {
   return AMG_OK;
 }
 
+// R = P^T A for the 2x2x2 box P of level L (the restriction of k_restrict_product), in slices
+// aligned on each aggregate's first row, whatever their padding (small ragged levels pad more
+// than 10%, but one pass over R still costs less than the residual's pass over A).  Left empty
+// (the residual and the sum over children are used instead) when a slice has more than 64
+// offsets.
+int restriction_product(Handle* h, hipStream_t s, Level& L) {
+  CsrHold Ph, PhT, R;
+  AMGP_TRY(tentative_prolongator(s, L.n, L.nc, L.agg, &Ph.c));
+  AMGP_TRY(transpose(s, Ph.c, &PhT.c));
+  AMGP_TRY(spgemm(s, PhT.c, level_csr(L), &R.c, h->dflag));
+  const int rc =
+      build_ell_aligned(s, L.nc, R.c.ptr, R.c.col, R.c.val, &L.R64, L.children, kMaxChildren, L.n, true);
+  return rc == AMG_EINVAL ? AMG_OK : rc;
+}
+
 int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const double* val,
           const amg_opts* o, hipStream_t s) {
   h->nbatch = o->nbatch > 0 ? o->nbatch : 1;
@@ -722,6 +742,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
       C.csr_col = cc.col;
       C.csr_val = cc.val;
       C.nnz = cc.nnz;
+      if (rc == AMG_OK) rc = restriction_product(h, s, L);
       if (rc != AMG_OK) {
         h->lv.push_back(C);  // owned by the handle from here on, also on error
         return rc;
@@ -756,6 +777,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     AMGP_TRY(alloc_vecs(L.v64, L.n, l > 0));
     if (h->precision == AMG_FP32) {
       AMGP_TRY(build_ell32(s, L.A64, &L.A32));
+      if (L.R64.val) AMGP_TRY(build_ell32(s, L.R64, &L.R32));
       if (L.general) {
         AMGP_TRY(build_ell32(s, L.P64, &L.P32));
         AMGP_TRY(build_ell32(s, L.PT64, &L.PT32));
@@ -979,6 +1001,15 @@ int amg_level_layout(const amg_handle* h, int level, int64_t* h_padded, int* h_l
   if (h_padded) *h_padded = A.padded;
   if (h_lanes) *h_lanes = A.group;
   if (h_aligned) *h_aligned = A.doff != nullptr;
+  return AMG_OK;
+}
+
+int amg_level_transfer(const amg_handle* h, int level, int* h_form, int64_t* h_stored) {
+  if (!h || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;
+  const amgp::Level& L = h->impl.lv[level];
+  const int form = L.general ? AMG_TRANSFER_EXPLICIT : (L.R64.val ? AMG_TRANSFER_PRODUCT : AMG_TRANSFER_RESIDUAL);
+  if (h_form) *h_form = form;
+  if (h_stored) *h_stored = form == AMG_TRANSFER_EXPLICIT ? L.PT64.padded : (form == AMG_TRANSFER_PRODUCT ? L.R64.padded : 0);
   return AMG_OK;
 }
 

@@ -481,3 +481,54 @@ def sp_random_graph(n, deg, rng):
     Lap.sort_indices()
     return W.CSR(n=n, row_ptr=Lap.indptr.astype(np.int32), col=Lap.indices.astype(np.int32),
                  val=Lap.data.astype(np.float64), grid=(n, 1, 1))
+
+
+@pytest.mark.parametrize("case", ["poisson_ragged", "q1_odd", "fv_batch", "poisson2d"])
+def test_restriction_product(amg, case):
+    """Box levels restrict with the product R = P^T A (b_c = P^T b - R x, no fine residual), stored
+    in slices aligned on each aggregate's first row: 7-point levels keep at most 32 offsets per
+    slice, 27-point ones at most 64.  On every level, in FP64 and FP32, b_c matches the oracle's
+    P^T (b - A x); the smoothed prolongator reports its explicit transpose instead."""
+    torch = torch_cuda()
+    nbatch, mc, width = 1, 40, 32
+    if case == "poisson_ragged":
+        A = W.poisson3d_7pt(17, 10, 13)
+    elif case == "q1_odd":
+        A = W.q1_27pt(13, 9, 11)
+        width = 64
+    elif case == "fv_batch":
+        A = W.stack_block_diagonal([_fv((9, 8, 6), s, 40 + p) for p, s in enumerate((0.5, 2.0))])
+        nbatch, mc = 2, 8
+    else:
+        A = W.poisson2d_5pt(45, 38)
+        width = 16
+    H = OA.build_hierarchy(A.to_scipy(), A.grid, nbatch=nbatch, max_coarse=mc)
+    for prec, tol in ((amg.AMG_FP64, 1e-14), (amg.AMG_FP32, 2e-6)):
+        with hierarchy(A, nbatch=nbatch, max_coarse=mc, precision=prec) as h:
+            assert amg.amg_num_levels(h) == len(H.levels) >= 3
+            for l in range(len(H.levels) - 1):
+                form, stored = amg.amg_level_transfer(h, l)
+                n, nc = H.levels[l].A.shape[0], H.levels[l + 1].A.shape[0]
+                assert form == amg.AMG_TRANSFER_PRODUCT, (l, form)
+                assert stored % 64 == 0 and stored <= width * ((nc + 63) // 64 * 64), (l, stored)
+                rng = np.random.default_rng(50 + l)
+                b, x = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+                ref = H.levels[l].P.T @ (b - H.levels[l].A @ x)
+                if prec == amg.AMG_FP64:
+                    bc = nan_vec(nc)
+                    amg.amg_restrict_residual(h, l, dev(b), dev(x), bc)
+                    torch.cuda.synchronize()
+                    assert relerr(host(bc), ref) <= tol, (l, relerr(host(bc), ref))
+            if prec == amg.AMG_FP32:
+                # the FP32 V-cycle restricts with the float copy of R: one cycle against the oracle
+                z = nan_vec(A.n)
+                r = W.rhs_uniform(A.n, 77)
+                amg.vcycle_apply(h, 2, 3, dev(r), z)
+                torch.cuda.synchronize()
+                zo = OA.vcycle(H, r, 2, 3, oracle_params(2, 3)[0])
+                assert relerr(host(z), zo) <= 1e-4
+    with hierarchy(W.poisson3d_7pt(12), max_coarse=100, smoothed=True) as h:
+        assert amg.amg_level_transfer(h, 0)[0] == amg.AMG_TRANSFER_EXPLICIT
+    with pytest.raises(amg.AmgError):
+        with hierarchy(W.poisson3d_7pt(8), max_coarse=100) as h:
+            amg.amg_level_transfer(h, amg.amg_num_levels(h) - 1)
