@@ -18,6 +18,8 @@ constexpr int kDenseTile = 64;   // dense coarsest level padded to a multiple of
 // coarse levels of 16..63 entries per row and at least this many rows take the offset-aligned
 // layout (one row per lane, no column indices) when their slices allow it
 constexpr int64_t kAlignedWideMinRows = int64_t(1) << 18;
+// FP32 offset-aligned slices of at least this many steps store each lane's steps in quads
+constexpr int kQuadMinSteps = 16;
 
 // Sliced ELLPACK matrix with G = `group` lanes per row (G in {1, 4, 16, 64}): a
 // slice holds 64 / G rows, one wavefront's worth.  Entry j of row r of slice s
@@ -35,8 +37,9 @@ constexpr int64_t kAlignedWideMinRows = int64_t(1) << 18;
 // 12 bytes per stored FP64 entry (`col` is null).  Each lane's steps are kept in
 // pairs: steps 2q and 2q + 1 of lane l sit at 128 q + 2 l and 128 q + 2 l + 1 of
 // the slice (an odd last step t at 64 t + l), so that one 16-byte (FP64) or
-// 8-byte (FP32) load per lane serves two steps; the FP32 copy keeps the
-// positions of the FP64 values.
+// 8-byte (FP32) load per lane serves two steps.  The FP32 copy of a slice of 16
+// or more steps keeps them in quads instead (steps 4q .. 4q + 3 of lane l at
+// 256 q + 4 l, then a pair, then a single step), one 16-byte load per four steps.
 template <typename T>
 struct Ell {
   int64_t n = 0;

@@ -204,6 +204,25 @@ __global__ void k_round_f32(int64_t m, const double* __restrict__ a, float* __re
   if (i < m) b[i] = (float)a[i];
 }
 
+// FP32 copy of offset-aligned slices: slices of at least kQuadMinSteps steps put each lane's steps in
+// quads (step t of lane l at 64 (t - t % 4) + 4 l + t % 4 for t below w - w % 4, then a pair at
+// 64 (t - t % 2) + 2 l + t % 2, then a single step at 64 t + l), narrower ones keep the FP64 pairs.
+__global__ void k_round_f32_aligned(int64_t nslices, const int32_t* __restrict__ sptr, const double* __restrict__ a,
+                                    float* __restrict__ b) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = g >> 6;
+  const int lane = (int)(g & 63);
+  if (s >= nslices) return;
+  const int beg = sptr[s];
+  const int w = (sptr[s + 1] - beg) >> 6;
+  const int w2 = w & ~1, w4 = w >= kQuadMinSteps ? (w & ~3) : 0;
+  for (int t = 0; t < w; ++t) {
+    const int pair = t < w2 ? 64 * (t & ~1) + 2 * lane + (t & 1) : 64 * t + lane;
+    const int dst = t < w4 ? 64 * (t & ~3) + 4 * lane + (t & 3) : pair;
+    b[beg + dst] = (float)a[beg + pair];
+  }
+}
+
 
 // Box aggregates of edge e: row (i, j, k) of problem p -> coarse (i/e, j/e, k/e) of
 // problem p; an axis of extent 1 is not coarsened.  For e = 2, children[I*8 + c]
@@ -493,8 +512,11 @@ int build_ell32(hipStream_t s, const Ell<double>& a, Ell<float>* out) {
     if (hipMalloc(&e.doff, sizeof(int32_t) * std::max<int64_t>(e.padded / kSlice, 1)) != hipSuccess) return AMG_ENOMEM;
     AMGP_HIP(hipMemcpyAsync(e.doff, a.doff, sizeof(int32_t) * (e.padded / kSlice), hipMemcpyDeviceToDevice, s));
   }
-  // same positions in both precisions (the paired order of offset-aligned slices included)
-  hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
+  if (a.doff)
+    hipLaunchKernelGGL(k_round_f32_aligned, dim3(grid_for(e.nslices * kSlice)), dim3(kBlock), 0, s, e.nslices, e.sptr,
+                       a.val, e.val);
+  else
+    hipLaunchKernelGGL(k_round_f32, dim3(grid_for(e.padded)), dim3(kBlock), 0, s, e.padded, a.val, e.val);
   AMGP_HIP(hipGetLastError());
   *out = e;
   return AMG_OK;

@@ -5,7 +5,7 @@
 // Layout and launch shape: one row per lane, 256-thread blocks (4 waves), the
 // matrix in sliced ELL with 64-row slices so that every load of val/col by a
 // wavefront is one contiguous 512 B (float64) segment.  On levels of up to
-// 4.2M rows, blocks are remapped so that each of the 8 XCDs (which receive
+// 3.1M rows, blocks are remapped so that each of the 8 XCDs (which receive
 // workgroups round-robin) walks one contiguous range of rows: the neighbours
 // gathered by a row (the previous and next grid lines and planes) were then
 // recently touched by the same XCD and are served from its L2 instead of HBM.
@@ -28,7 +28,7 @@ inline unsigned xcd_grid(int64_t n) {
 }
 
 // Logical block index.  Block b runs on XCD b % 8.  For levels up to
-// kRemapMaxBlocks blocks (4.2M rows, a working set near the 256 MB MALL) each
+// kRemapMaxBlocks blocks (3.1M rows, a working set near the 256 MB MALL) each
 // XCD is given the contiguous blocks [x * G/8, (x+1) * G/8), so the
 // neighbouring planes a row gathers were recently touched by the same XCD and
 // hit its L2 (measured: 40.9 vs 44.8 us per fused step at 128^3).  Larger
@@ -41,7 +41,10 @@ inline unsigned xcd_grid(int64_t n) {
 // 64: 1.67, 400: 1.73) and within 1.5% of the fastest on the 7-point level at
 // 256^3; whole contiguous ranges per XCD are slower on both (1.79 ms; a
 // plane's reuse is then too far away in time).  G is a multiple of 8 (xcd_grid).
-constexpr unsigned kRemapMaxBlocks = 16384;
+// The threshold sits between the 128^3 fine level (8192 blocks, 235 MB per fused step, which
+// the hints below make 15-20% slower) and level 1 of the 27-point 320^3 problem (16000 blocks,
+// 1.1 GB per step: streaming it took the solve from 0.496 to 0.493 s).
+constexpr unsigned kRemapMaxBlocks = 12288;
 constexpr unsigned kXcdChunk = 128;
 
 __device__ __forceinline__ int64_t logical_block() {
@@ -93,24 +96,106 @@ __device__ __forceinline__ f32x2 ld2(const float* p) {
   if constexpr (NT) return __builtin_nontemporal_load(q); else return *q;
 }
 
+// FP32 slices of at least kQuadMinSteps steps keep each lane's steps in quads instead: steps 4q ..
+// 4q + 3 of lane l at 256 q + 4 l of the slice, then (w mod 4 >= 2) a pair at 64 t + 2 l, then (w odd)
+// a single step at 64 t + l, so that one 16-byte load serves four steps; narrower slices keep
+// the pairs.  Measured on the FP32 fused step: 27-point level at 320^3 776 us in quads (batches of
+// 12 steps) against 812 us in pairs one at a time; 7-point level at 256^3 150 us in pairs
+// (batches of 6) against 159 us one pair at a time and 157 us in quads.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ f32x4 ld4(const float* p) {
+  const f32x4* q = reinterpret_cast<const f32x4*>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q); else return *q;
+}
+
 // Sum over the steps t of an FP32 offset-aligned slice [beg, end) of val_t * g(column_t), in
-// ascending t (the order of the FP64 loops), for the row r served by this lane.
-template <bool NT, typename Gf>
+// ascending t (the order of the FP64 loops), for the row r served by this lane, with the requests
+// issued in batches as in the FP64 form below.  Batched = false: one load per iteration.
+template <bool NT, typename Gf, bool Batched = true>
 __device__ __forceinline__ float aligned_sum_f32(const float* __restrict__ val, int beg, int end, int lane,
                                                  const int32_t* __restrict__ off, int r, int last, Gf g) {
   const int w = (end - beg) >> 6;
   const float* v = val + beg;
+  auto col = [&](int t) { return min(max(r + off[t], 0), last); };
   float acc = 0.0f;
   int t = 0;
-#pragma unroll 2
-  for (; t + 1 < w; t += 2) {
-    const f32x2 p = ld2<NT>(v + 64 * t + 2 * lane);
-    const int c0 = min(max(r + off[t], 0), last);
-    const int c1 = min(max(r + off[t + 1], 0), last);
-    acc += p.x * g(c0);
-    acc += p.y * g(c1);
+  if (w >= kQuadMinSteps) {
+    constexpr int B = 12, H = B / 4;
+    const int w4 = w & ~3;
+    const int nb = Batched ? w4 / B : 0;
+    const float* vq = v + 4 * lane;  // quad u of batch q at vq + 64 (q B) + 256 u
+    f32x4 nxt[H];
+    if (nb > 0) {
+#pragma unroll
+      for (int u = 0; u < H; ++u) nxt[u] = ld4<NT>(vq + 256 * u);
+    }
+    for (int q = 0; q < nb; ++q, t += B) {
+      f32x4 cur[H];
+      float gv[B];
+#pragma unroll
+      for (int u = 0; u < H; ++u) cur[u] = nxt[u];
+#pragma unroll
+      for (int u = 0; u < B; ++u) gv[u] = g(col(t + u));
+      if (q + 1 < nb) {
+#pragma unroll
+        for (int u = 0; u < H; ++u) nxt[u] = ld4<NT>(vq + 64 * (t + B) + 256 * u);
+      }
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        acc += cur[u].x * gv[4 * u];
+        acc += cur[u].y * gv[4 * u + 1];
+        acc += cur[u].z * gv[4 * u + 2];
+        acc += cur[u].w * gv[4 * u + 3];
+      }
+    }
+    for (; t < w4; t += 4) {
+      const f32x4 p = ld4<NT>(vq + 64 * t);
+      acc += p.x * g(col(t));
+      acc += p.y * g(col(t + 1));
+      acc += p.z * g(col(t + 2));
+      acc += p.w * g(col(t + 3));
+    }
+    if (t + 1 < w) {
+      const f32x2 p = ld2<NT>(v + 64 * t + 2 * lane);
+      acc += p.x * g(col(t));
+      acc += p.y * g(col(t + 1));
+      t += 2;
+    }
+  } else {
+    constexpr int B = 6, H = B / 2;
+    const int wp = w & ~1;
+    const int nb = Batched ? wp / B : 0;
+    const float* vp = v + 2 * lane;  // pair u of batch q at vp + 64 (q B) + 128 u
+    f32x2 nxt[H];
+    if (nb > 0) {
+#pragma unroll
+      for (int u = 0; u < H; ++u) nxt[u] = ld2<NT>(vp + 128 * u);
+    }
+    for (int q = 0; q < nb; ++q, t += B) {
+      f32x2 cur[H];
+      float gv[B];
+#pragma unroll
+      for (int u = 0; u < H; ++u) cur[u] = nxt[u];
+#pragma unroll
+      for (int u = 0; u < B; ++u) gv[u] = g(col(t + u));
+      if (q + 1 < nb) {
+#pragma unroll
+        for (int u = 0; u < H; ++u) nxt[u] = ld2<NT>(vp + 64 * (t + B) + 128 * u);
+      }
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        acc += cur[u].x * gv[2 * u];
+        acc += cur[u].y * gv[2 * u + 1];
+      }
+    }
+    for (; t < wp; t += 2) {
+      const f32x2 p = ld2<NT>(vp + 64 * t);
+      acc += p.x * g(col(t));
+      acc += p.y * g(col(t + 1));
+    }
   }
-  if (t < w) acc += ld<NT>(v + 64 * t + lane) * g(min(max(r + off[t], 0), last));
+  if (t < w) acc += ld<NT>(v + 64 * t + lane) * g(col(t));
   return acc;
 }
 
@@ -543,7 +628,8 @@ __device__ __forceinline__ T ell_dot_any(EllView<T> A, int row, const T* __restr
   if (A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
     if constexpr (std::is_same_v<T, float>) {
-      return aligned_sum_f32<NT>(A.val, beg, end, row & 63, off, row, A.last, [&](int c) { return x[c]; });
+      auto g = [&](int c) { return x[c]; };
+      return aligned_sum_f32<NT, decltype(g), false>(A.val, beg, end, row & 63, off, row, A.last, g);
     } else {
       auto g = [&](int c) { return x[c]; };
       return aligned_sum_f64<NT, decltype(g), false>(A.val, beg, end, row & 63, off, row, A.last, g);

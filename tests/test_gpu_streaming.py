@@ -1,6 +1,6 @@
-"""Full-vector parity of the streaming kernels (levels above 16384 blocks of 256 rows).
+"""Full-vector parity of the streaming kernels (levels above 12288 blocks of 256 rows).
 
-Levels of more than 4.2M rows take kernels with nontemporal loads and stores
+Levels of more than 3.1M rows take kernels with nontemporal loads and stores
 and a block order that hands runs of 128 consecutive blocks to each XCD in
 turn; the blocks past the last whole round of 8 runs (1024 blocks) keep the
 launch order.  Every full-size workload runs its fine level on these kernels.
@@ -35,7 +35,7 @@ from oracle import smoothers as S  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-STREAM_MIN_BLOCKS = 16384
+STREAM_MIN_BLOCKS = 12288
 XCD_ROUND = 8 * 128  # blocks per round of XCD runs on streaming levels
 
 
