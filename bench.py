@@ -43,6 +43,7 @@ METRIC = "Smoother HBM GB/s (% peak); AMG-PCG time to 1e-8 residual, learned/FP3
 PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 KIND_NAMES = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
 FUSED_PROLONG_MAX_ROWS = 1 << 20  # box levels up to this size carry the prolongation in the smoother
+STREAM_MIN_BLOCKS = 12288  # levels above this many 256-row blocks take the streaming kernels
 
 
 # ---------------------------------------------------------------------------
@@ -342,6 +343,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="q1_27pt", choices=("q1_27pt", "poisson_7pt", "fv_diffusion"),
+                    help="the matrix: the 27-point Q1 Laplacian (the headline), the 7-point Poisson problem or "
+                         "the variable-coefficient diffusion problem (sigma = 1)")
     ap.add_argument("--size", type=int, default=320)
     ap.add_argument("--kind", type=int, default=2)
     ap.add_argument("--degree", type=int, default=4)
@@ -370,7 +374,7 @@ def main():
     stream = torch.cuda.current_stream()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     t0 = time.perf_counter()
-    A, b, _ = W.config_problem(5, size=args.size)
+    A, b, _ = W.config_problem({"q1_27pt": 5, "poisson_7pt": 2, "fv_diffusion": 3}[args.workload], size=args.size)
     assembly_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
@@ -428,9 +432,11 @@ def main():
     padded, lanes, aligned = amg.amg_level_layout(h, 0)
     csr_bytes = csr_model_step(nnz0, n0)
     ceil = ceiling(amg, stream)
+    streams = ((n0 + 255) // 256 + 7) // 8 * 8 > STREAM_MIN_BLOCKS
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
-                "kernel": f"k_fused<double,0,true,true,1> (fine level, {args.size}^3, 27-point)",
+                "kernel": f"k_fused<double,0,true,{str(streams).lower()},1> (fine level, {args.workload} "
+                          f"{args.size}^3)",
                 "bytes_per_launch": int(step_bytes), "avg_launch_us": round(t_step * 1e3, 2),
                 "layout": {"stored_entries": int(padded), "lanes_per_row": lanes, "offset_aligned": aligned,
                            "bytes_per_launch": "8 per stored entry + 4 per 64 + 56 per row"},
@@ -439,7 +445,7 @@ def main():
                               "note": "counts column indices and row pointers the offset-aligned layout "
                                       "does not read"},
                 "ceiling": ceil, "frac_of_read_ceiling": round(achieved / ceil["read_GBps"], 4)}
-    traffic = measured_traffic(args.size)
+    traffic = measured_traffic(args.size) if args.workload == "q1_27pt" else None
     if traffic is not None:
         roofline["traffic"] = traffic
 
@@ -500,7 +506,7 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"q1_27pt_{args.size}^3_amg_pcg_to_1e-8",
+        "config": {"workload": f"{args.workload}_{args.size}^3_amg_pcg_to_1e-8",
                    "smoother": KIND_NAMES[args.kind], "degree": args.degree, "n": int(n0), "nnz": int(nnz0),
                    "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2), "upload_s": round(upload_s, 3),
                    "setup_s": round(setup_s, 3)},
