@@ -127,6 +127,29 @@ def test_poly_pcg_history_matches_oracle(amg):
                 assert relerr(host(x), ro.x) <= 1e-9
 
 
+def test_poly_pcg_gap_history_matches_oracle(amg):
+    """The ill-conditioned gap spectrum at N = 256 (condition number 1e9), where the iteration
+    counts themselves depend on rounding: the first 20 residuals of the smoother-preconditioned CG
+    match the oracle's to 1e-8 for every kind and degrees 1, 2, 4, 6 and 8.  Over those 20
+    iterations the oracle moves by at most 6e-11 when b is perturbed by one ulp per entry; it
+    departs from itself by more than 1e-8 only after 30 to 49 iterations."""
+    torch = torch_cuda()
+    A, b, _ = W.qdq_dense(256, "gap")
+    Ad = A.to_scipy().toarray()
+    Minv = S.l1_diagonal(A.to_scipy())
+    m = 20
+    with hierarchy(A, max_coarse=4096) as h:
+        for kind in KINDS:
+            for k in (1, 2, 4, 6, 8):
+                x = nan_vec(A.n)
+                rc, it, rel, hist = amg.pcg_solve_smoother(h, kind, k, dev(b), x, True, 1e-5, 5000, False, True)
+                torch.cuda.synchronize()
+                beta, a = oracle_params(kind, k)
+                ro = OA.pcg(Ad, b, lambda r: S.smooth(Ad, Minv, r, None, kind, k, beta, a), 1e-5, 5000)
+                assert rc == amg.AMG_OK and it > m and ro.iters > m, (kind, k, it, ro.iters)
+                assert np.allclose(hist[:m + 1], ro.history[:m + 1], rtol=1e-8, atol=0), (kind, k)
+
+
 def test_aniso_hierarchy_and_vcycle(amg):
     """Odd x extent (N + 1 nodes): the last aggregate of every grid line is one node wide."""
     torch = torch_cuda()
