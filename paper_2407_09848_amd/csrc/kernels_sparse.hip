@@ -351,7 +351,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 //   x  += wprev g_old + g
 // g_old is gathered by neighbouring rows, so g is written to the other buffer
 // of a ping-pong pair; r and x are row-local and updated in place.  wprev
-// carries an x update deferred by a first step that gathered x itself.
+// carries an x update deferred by the previous step (a first step that gathered
+// x itself, or a step launched with x = null, which leaves x alone: the next
+// step adds both directions, which it reads anyway, in the same order).
 // STORE = false on the last step of an application: only x is needed.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, bool STORE, bool NT, int G>
@@ -370,9 +372,11 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
   const T ri = ld<NT>(rin + i);
   const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
-  T xi = ld<NT>(x + i);
-  if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
-  st<NT>(x + i, xi + wprev * go + w * g);
+  if (x) {
+    T xi = ld<NT>(x + i);
+    if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
+    st<NT>(x + i, xi + wprev * go + w * g);
+  }
   if (STORE) {
     st<NT>(rout + i, r);
     gnew[i] = g;
