@@ -525,6 +525,7 @@ def main():
                    "smoother": KIND_NAMES[args.kind], "degree": args.degree, "n": int(n0), "nnz": int(nnz0),
                    "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2), "upload_s": round(upload_s, 3),
                    "setup_s": round(setup_s, 3)},
+        "value_frac_of_read_ceiling": round(value / ceil["read_GBps"], 4),
         "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
         "learned": learned_info, "diffusion_256": c3,
     }
