@@ -205,8 +205,10 @@ int amg_spmv(amg_handle* h, int level, const double* d_x, double* d_y, void* str
 int smoother_apply(amg_handle* h, int level, int kind, int degree, const double* d_b,
                    double* d_x, int x_is_zero, void* stream);
 
-/* b_c = P_l^T (b - A_l x): fused residual and restriction to level l+1 (Section 2, eq. amg).
- * d_b, d_x have n_l entries, d_bc has n_{l+1}. */
+/* b_c = P_l^T (b - A_l x): the restriction of the residual to level l+1 (Section 2, eq. amg),
+ * computed as P_l^T b - (P_l^T A_l) x on box levels with a restriction product
+ * (amg_level_transfer), else from the residual.  d_b, d_x have n_l entries, d_bc has n_{l+1}.
+ * Asynchronous; AMG_EINVAL for a null pointer or the coarsest level. */
 int amg_restrict_residual(amg_handle* h, int level, const double* d_b, const double* d_x,
                           double* d_bc, void* stream);
 
