@@ -12,8 +12,9 @@ value        = bytes one solve must move in the storage layouts the kernels use
                solve) / the solve's wall time, GB/s;
 roofline     = the fine-level fused recurrence step (k_fused<double,0,true,true,1>):
                the bytes it must move per launch / its average duration, timed
-               here with events on the launch stream (degree-6 minus degree-3
-               smoother applications from x = 0 = three fused steps); beside it
+               here with events on the launch stream (degree-5 minus degree-4
+               and degree-7 minus degree-6 smoother applications from x = 0,
+               each one such step); beside it
                the per-step figure of the CSR byte model (12 nnz + 60 n), and
                the measured ceiling of this GPU (the library's plain read and
                copy kernels);
@@ -437,11 +438,12 @@ def main():
         t, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, args.kind, k, bd, xs, True), reps)
         return t
 
-    t6, t3 = time_apply(6), time_apply(3)
-    t_step = (t6 - t3) / 3.0
-    # degree 6 minus degree 3: three stored steps, two of which leave x alone (x is updated on
-    # every other step), so the bytes per launch are the average over that mix
-    step_bytes = (2 * fused_bytes(n0, M0, 8, True, False) + fused_bytes(n0, M0, 8, True, True)) // 3
+    # x is updated on every other step: from x = 0, degree 5 minus degree 4 and degree 7 minus
+    # degree 6 each add one stored step that updates x (the step k_fused<...> of the trace;
+    # the steps between them, which leave x alone, are k_fused_keep_x)
+    t4, t5, t6, t7 = (time_apply(k) for k in (4, 5, 6, 7))
+    t_step = ((t5 - t4) + (t7 - t6)) / 2.0
+    step_bytes = fused_bytes(n0, M0, 8, True, True)
     achieved = step_bytes / (t_step * 1e-3) / 1e9
     padded, lanes, aligned = amg.amg_level_layout(h, 0)
     csr_bytes = csr_model_step(nnz0, n0)
@@ -453,8 +455,7 @@ def main():
                           f"{args.size}^3)",
                 "bytes_per_launch": int(step_bytes), "avg_launch_us": round(t_step * 1e3, 2),
                 "layout": {"stored_entries": int(padded), "lanes_per_row": lanes, "offset_aligned": aligned,
-                           "bytes_per_launch": "8 per stored entry + 4 per 64 + 56 per row (40 on the steps "
-                                               "that leave x alone, two in three of the stored steps)"},
+                           "bytes_per_launch": "8 per stored entry + 4 per 64 + 56 per row"},
                 "csr_model": {"bytes_per_launch": int(csr_bytes), "formula": "12 nnz + 60 n",
                               "GBps": round(csr_bytes / (t_step * 1e-3) / 1e9, 1),
                               "note": "counts column indices and row pointers the offset-aligned layout "

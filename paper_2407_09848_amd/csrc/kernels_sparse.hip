@@ -352,27 +352,26 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 // g_old is gathered by neighbouring rows, so g is written to the other buffer
 // of a ping-pong pair; r and x are row-local and updated in place.  wprev
 // carries an x update deferred by the previous step (a first step that gathered
-// x itself, or a step launched with x = null, which leaves x alone: the next
-// step adds both directions, which it reads anyway, in the same order).
+// x itself, or a k_fused_keep_x step, which leaves x alone: the next step adds
+// both directions, which it reads anyway, in the same order).
 // STORE = false on the last step of an application: only x is needed.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool STORE, bool NT, int G>
-__global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
-                                                  const T* __restrict__ gold, T* __restrict__ gnew,
-                                                  const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
-                                                  T wprev, Wt wv, Wt wpv, Prol<T> pr) {
+template <typename T, int MODE, bool STORE, bool NT, int G, bool XUPD>
+__device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                          const T* __restrict__ gold, T* __restrict__ gnew, const T* rin, T* rout,
+                                          T* __restrict__ x, T alpha, T c, T w, T wprev, Wt wv, Wt wpv, Prol<T> pr) {
   const int64_t i = row_of_thread<G>();
   if (exit_rows<G>(i, n)) return;
   const T ag = ell_dot<NT, G>(A, i, gold);
   if (!row_owner<G>(i, n)) return;
-  w = wsel(wv, w, i);
-  wprev = wsel(wpv, wprev, i);
   const T mi = ld<NT>(minv + i);
   const T go = gold[i];
   const T ri = ld<NT>(rin + i);
   const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
-  if (x) {
+  if constexpr (XUPD) {
+    w = wsel(wv, w, i);
+    wprev = wsel(wpv, wprev, i);
     T xi = ld<NT>(x + i);
     if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
     st<NT>(x + i, xi + wprev * go + w * g);
@@ -381,6 +380,24 @@ __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const
     st<NT>(rout + i, r);
     gnew[i] = g;
   }
+}
+
+template <typename T, int MODE, bool STORE, bool NT, int G>
+__global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                  const T* __restrict__ gold, T* __restrict__ gnew,
+                                                  const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
+                                                  T wprev, Wt wv, Wt wpv, Prol<T> pr) {
+  fused_step<T, MODE, STORE, NT, G, true>(n, A, minv, gold, gnew, rin, rout, x, alpha, c, w, wprev, wv, wpv, pr);
+}
+
+// A stored step that leaves x alone: the next step adds this step's weighted direction (which it
+// reads anyway as its own old direction) together with its own.
+template <typename T, int MODE, bool NT, int G>
+__global__ __launch_bounds__(kBlock) void k_fused_keep_x(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                         const T* __restrict__ gold, T* __restrict__ gnew,
+                                                         const T* rin, T* rout, T alpha, T c) {
+  fused_step<T, MODE, true, NT, G, false>(n, A, minv, gold, gnew, rin, rout, nullptr, alpha, c, T(0), T(0), Wt(),
+                                          Wt(), Prol<T>());
 }
 
 // END fused-step
@@ -1093,6 +1110,13 @@ template <typename T, bool NT, int G>
 void go_fused(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv, const T* gold,
               T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv, Prol<T> pr) {
   dim3 bl(kBlock);
+  if (!x) {  // a stored step that leaves x alone (the caller only passes null x with store set)
+    if (mode == 0)
+      hipLaunchKernelGGL((k_fused_keep_x<T, 0, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
+    else
+      hipLaunchKernelGGL((k_fused_keep_x<T, 1, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
+    return;
+  }
   if (mode == 0 && store)
     hipLaunchKernelGGL((k_fused<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
                        wp_, wv, wpv, pr);
