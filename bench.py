@@ -174,6 +174,22 @@ def event_time(stream, fn, reps):
     return e0.elapsed_time(e1) / reps, out
 
 
+def fused_step_time(amg, h, kind, bd, xs, stream, reps=10):
+    """Average duration (ms) of the fine level's stored fused step that updates x, from smoother
+    applications on level 0 from x = 0 timed with events on the launch stream.  x is updated on
+    every other step, so degree 5 minus degree 4 and degree 7 minus degree 6 each add one such
+    step (k_fused<...> in a kernel trace; the steps between them, which leave x alone, are
+    k_fused_keep_x)."""
+    def time_apply(k):
+        for _ in range(2):
+            amg.smoother_apply(h, 0, kind, k, bd, xs, True)
+        t, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, kind, k, bd, xs, True), reps)
+        return t
+
+    t4, t5, t6, t7 = (time_apply(k) for k in (4, 5, 6, 7))
+    return ((t5 - t4) + (t7 - t6)) / 2.0
+
+
 def true_relres(amg, h, bd, x):
     """||b - A x|| / ||b|| with the library's level-0 product (a check, not part of the path)."""
     import torch
@@ -315,6 +331,18 @@ def c3_variant(amg, W, stream):
         tm, (rc, it, _, _) = event_time(stream, lambda: amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 1000, flex), 3)
         out[name] = {"ms": round(tm, 3), "iters": it, "setup_s": round(st, 3),
                      "true_relres": true_relres(amg, h, bd, x)}
+        if prec == amg.AMG_FP64:
+            # the fine level's x-updating fused step on this 7-point level (the same kernel as the
+            # headline's, 7 stored entries per row)
+            n0 = amg.amg_level_info(h, 0)[0]
+            M0 = matrix_bytes(amg, h, 0, 8)
+            xw = torch.zeros(n0, dtype=torch.float64, device="cuda")
+            t_step = fused_step_time(amg, h, 2, bd, xw, stream)
+            step_bytes = fused_bytes(n0, M0, 8, True, True)
+            achieved = step_bytes / (t_step * 1e-3) / 1e9
+            out["fused_step"] = {"avg_launch_us": round(t_step * 1e3, 2), "bytes_per_launch": int(step_bytes),
+                                 "GBps": round(achieved, 1), "frac_of_peak": round(achieved / PEAK_HBM, 4)}
+            del xw
         xs[name] = x
         amg.amg_destroy(h)
     out["fp32_vs_fp64_time"] = round(out["fp32"]["ms"] / out["fp64"]["ms"], 3)
@@ -428,21 +456,9 @@ def main():
     M0 = lv64[0][1]
     value = solve_bytes(lv64, M0, 8, args.kind, args.degree, it, False) / (ms * 1e-3) / 1e9
 
-    # ---- the fine level's fused step: degree 6 minus degree 3 from x = 0 = three stored steps ----
+    # ---- the fine level's fused step ----
     xs = torch.zeros(n0, dtype=torch.float64, device="cuda")
-    reps = 10
-
-    def time_apply(k):
-        for _ in range(2):
-            amg.smoother_apply(h, 0, args.kind, k, bd, xs, True)
-        t, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, args.kind, k, bd, xs, True), reps)
-        return t
-
-    # x is updated on every other step: from x = 0, degree 5 minus degree 4 and degree 7 minus
-    # degree 6 each add one stored step that updates x (the step k_fused<...> of the trace;
-    # the steps between them, which leave x alone, are k_fused_keep_x)
-    t4, t5, t6, t7 = (time_apply(k) for k in (4, 5, 6, 7))
-    t_step = ((t5 - t4) + (t7 - t6)) / 2.0
+    t_step = fused_step_time(amg, h, args.kind, bd, xs, stream)
     step_bytes = fused_bytes(n0, M0, 8, True, True)
     achieved = step_bytes / (t_step * 1e-3) / 1e9
     padded, lanes, aligned = amg.amg_level_layout(h, 0)
