@@ -23,8 +23,11 @@ cpu_baseline = the FP64 CPU oracle applying the same smoother (degree 4, from
                the same byte model; its result is compared with the GPU's;
 variants     = time to 1e-8 of the other three variants of this workload (FP32
                hierarchy inside FP64 CG, learned weights, optimal 1st kind),
-               of the remaining smoother kinds, and the FP32-against-FP64
-               comparison on the 256^3 variable-coefficient diffusion problem.
+               of the remaining smoother kinds, of the same operator with its
+               stored zero entries eliminated (a 21-point pattern: the same
+               iterates, bitwise), and the FP32-against-FP64 comparison on the
+               256^3 variable-coefficient diffusion problem (with its fine
+               level's fused step).
 """
 from __future__ import annotations
 
@@ -391,10 +394,11 @@ def main():
     ap.add_argument("--kind", type=int, default=2)
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--variants", default="fp32,learned,kinds,c3",
+    ap.add_argument("--variants", default="fp32,learned,kinds,zeros,c3",
                     help="comma-separated subset of the variants to time: fp32 (the FP32 hierarchy), learned "
-                         "(the trained network's weights), kinds (the other smoother kinds), c3 (FP32 against "
-                         "FP64 on the 256^3 diffusion problem); empty for none")
+                         "(the trained network's weights), kinds (the other smoother kinds), zeros (the 27-point "
+                         "operator with its stored zero entries eliminated), c3 (FP32 against FP64 on the 256^3 "
+                         "diffusion problem); empty for none")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--counter-sample", action="store_true",
                     help="setup, three smoother applications of degree 6 on the fine level and one 1 GiB copy "
@@ -451,6 +455,7 @@ def main():
     _, _, _, hist = amg.pcg_solve(h, args.kind, args.degree, bd, x, True, 1e-8, 1000, False, True)
     solve_info = {"iters": len(hist) - 1, "relres_history": [float(f"{v:.4e}") for v in hist],
                   "true_relres": true_relres(amg, h, bd, x)}
+    x_head = x.clone()
     L = amg.amg_num_levels(h)
     lv64 = level_table(amg, h, 8)
     M0 = lv64[0][1]
@@ -509,6 +514,23 @@ def main():
             "ms": round(tm, 3), "iters": itv, "setup_s": round(s32, 3), "outer": "FP64 flexible CG",
             "true_relres": true_relres(amg, h, bd, x)}
         amg.amg_destroy(h32)
+    if "zeros" in chosen and args.workload == "q1_27pt":
+        # the same operator without its stored zero face entries (21-point pattern), as a caller
+        # gets it by eliminating stored zeros: same hierarchy below the fine level, same iterates
+        t0 = time.perf_counter()
+        Bz = W.q1_27pt(args.size, store_zeros=False)
+        asm_z = time.perf_counter() - t0
+        rpz, clz, vlz = dev(Bz.row_ptr), dev(Bz.col), dev(Bz.val)
+        hz = amg.amg_setup(rpz, clz, vlz, *Bz.grid, 1, 4096, amg.AMG_FP64)
+        torch.cuda.synchronize()
+        tm, itv = time_solve(hz, args.kind, args.degree)
+        variants[f"fp64_{KIND_NAMES[args.kind]}_k{args.degree}_zeros_eliminated"] = {
+            "ms": round(tm, 3), "iters": itv, "nnz": int(Bz.nnz), "assembly_s": round(asm_z, 2),
+            "fine_level_stored_entries": int(amg.amg_level_layout(hz, 0)[0]),
+            "solution_bitwise_equal": bool(torch.equal(x, x_head))}
+        amg.amg_destroy(hz)
+        del rpz, clz, vlz, Bz
+        torch.cuda.empty_cache()
     learned_info = None
     if "learned" in chosen and args.kind == 2:
         params, learned_info = train_learned(args, amg, W)

@@ -190,3 +190,58 @@ def test_aniso_pcg_iterations_256(amg):
             assert rc == amg.AMG_OK and it == it_o, (kind, k, it, it_o)
             assert rel == pytest.approx(rel_o, rel=1e-3)
             assert np.linalg.norm(b - A.to_scipy() @ host(x)) <= 1.05e-8 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("n", [96, 164])
+def test_q1_stored_zeros_leave_results_unchanged(amg, n):
+    """The 27-point Q1 operator with its six zero face entries per row stored, and without them
+    (the 21-point pattern a caller gets by eliminating stored zeros): the coarse levels are the
+    same matrices, and the smoothers, the V-cycle and PCG return bitwise the same vectors, since
+    a zero product leaves each row sum unchanged.  164^3 runs the streaming kernels."""
+    torch = torch_cuda()
+    A, B = W.q1_27pt(n), W.q1_27pt(n, store_zeros=False)
+    assert B.nnz < A.nnz
+    b = W.rhs_uniform(A.n, 41)
+    x0 = W.rhs_uniform(A.n, 42)
+    bd = dev(b)
+    out = {}
+    for name, M in (("stored", A), ("eliminated", B)):
+        res = {}
+        with hierarchy(M) as h:
+            L = amg.amg_num_levels(h)
+            res["levels"] = [amg.amg_level_info(h, l) for l in range(L)]
+            res["layout0"] = amg.amg_level_layout(h, 0)
+            res["export"] = [tuple(host(t) for t in amg.amg_level_export(h, l)) for l in range(L)]
+            for kind in KINDS:
+                x = nan_vec(A.n)
+                amg.smoother_apply(h, 0, kind, 4, bd, x, True)
+                res[("smooth0", kind)] = host(x)
+                x = dev(x0)
+                amg.smoother_apply(h, 0, kind, 3, bd, x, False)
+                res[("smooth", kind)] = host(x)
+            for kind in (2, 3):
+                z = nan_vec(A.n)
+                amg.vcycle_apply(h, kind, 4, bd, z)
+                res[("vcycle", kind)] = host(z)
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, 2, 4, bd, x, True, 1e-8, 1000)
+            torch.cuda.synchronize()
+            assert rc == amg.AMG_OK
+            res["pcg"] = (it, rel, host(x))
+        out[name] = res
+    s, e = out["stored"], out["eliminated"]
+    assert [lv[0] for lv in s["levels"]] == [lv[0] for lv in e["levels"]]
+    assert s["levels"][0][1] == A.nnz and e["levels"][0][1] == B.nnz
+    assert s["levels"][1:] == e["levels"][1:]
+    assert e["layout0"][2] and e["layout0"][0] < s["layout0"][0]
+    # level 0: same l1 diagonal; coarser levels: the same CSR matrices and diagonals, bitwise
+    assert np.array_equal(s["export"][0][3], e["export"][0][3])
+    for l in range(1, len(s["levels"])):
+        for a_, b_ in zip(s["export"][l], e["export"][l]):
+            assert np.array_equal(a_, b_), l
+    for key in s:
+        if isinstance(key, tuple):
+            assert np.array_equal(s[key], e[key]), key
+    assert s["pcg"][0] == e["pcg"][0] and s["pcg"][1] == e["pcg"][1]
+    assert np.array_equal(s["pcg"][2], e["pcg"][2])
+    print(f"Q1 {n}^3: {A.nnz} vs {B.nnz} stored entries, {s['pcg'][0]} iterations either way", flush=True)

@@ -53,6 +53,18 @@ def test_q1_27pt_is_kronecker_sum_of_stiffness_and_mass(n):
     assert np.all(A.val[face] == 0.0) and face.sum() > 0
 
 
+@pytest.mark.parametrize("n", [3, 6])
+def test_q1_without_stored_zeros_is_the_same_operator(n):
+    A, B = W.q1_27pt(n), W.q1_27pt(n, store_zeros=False)
+    S = A.to_scipy().copy()
+    S.eliminate_zeros()
+    assert np.array_equal(S.indptr, B.row_ptr) and np.array_equal(S.indices, B.col)
+    assert np.array_equal(S.data, B.val)
+    # 27 minus the six faces per interior row; in all, the face pairs of the grid are gone
+    faces = 3 * (n - 1) * n * n
+    assert B.nnz == A.nnz - 2 * faces
+
+
 def test_fv_constant_conductivity_closed_form():
     shape = (4, 5, 6)  # (nz, ny, nx)
     c = 2.5

@@ -143,13 +143,15 @@ def poisson3d_7pt(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
     return stencil_csr((nx, ny, nz), offs, vals)
 
 
-def q1_27pt(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
+def q1_27pt(nx: int, ny: int | None = None, nz: int | None = None, store_zeros: bool = True) -> CSR:
     """3D trilinear (Q1) finite-element Laplacian on a uniform hexahedral mesh.
 
     Stencil (mesh-size factor dropped): centre 8/3, the 6 face neighbours 0
     (stored explicitly, they belong to the 27-point pattern), the 12 edge
     neighbours -1/6, the 8 corner neighbours -1/12.  Values are taken from
-    exact rationals and rounded once to float64.
+    exact rationals and rounded once to float64.  store_zeros=False leaves the
+    six zero face entries out (the same operator with a 21-point pattern, what
+    a caller gets by eliminating stored zeros).
     """
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
@@ -159,6 +161,8 @@ def q1_27pt(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
             for dx in (-1, 0, 1):
                 d = abs(dx) + abs(dy) + abs(dz)
                 v = {0: Fraction(8, 3), 1: Fraction(0), 2: Fraction(-1, 6), 3: Fraction(-1, 12)}[d]
+                if v == 0 and not store_zeros:
+                    continue
                 offs.append((dx, dy, dz))
                 vals.append(float(v))
     return stencil_csr((nx, ny, nz), offs, vals)
