@@ -27,7 +27,9 @@ variants     = time to 1e-8 of the other three variants of this workload (FP32
                stored zero entries eliminated (a 21-point pattern: the same
                iterates, bitwise), and the FP32-against-FP64 comparison on the
                256^3 variable-coefficient diffusion problem (with its fine
-               level's fused step).
+               level's fused step); beside them the learned-weights
+               configuration (32 stacked 64^3 diffusion problems, degree 6):
+               training and held-out solves, plain against learned.
 """
 from __future__ import annotations
 
@@ -312,9 +314,75 @@ def learned_variant(args, amg, W, h, bd, x, stream, params):
             "level_betas": [[round(v, 6) for v in row] for row in lb]}
 
 
+def c4_variant(args, amg, W, stream):
+    """The learned-weights configuration at its own size and degree: 32 stacked 64^3 diffusion
+    problems (sigma 0.5, 1, 2 in turn), optimal 4th kind of degree 6 on an FP32 hierarchy, the
+    network trained through the adjoint of two V-cycles (Adam); then three held-out problems
+    (one per sigma, FP64 hierarchy) solved to 1e-8 with the plain and the learned weights (the
+    learned ones kept when they lower the problem's two-cycle ratio)."""
+    import torch
+
+    from paper_2407_09848_amd import learned
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    deg, P_ = 6, 32
+    sig = W.config4_sigmas(P_)
+    t0 = time.perf_counter()
+    mats = [W.fv_diffusion(np.exp(sig[p] * W.gaussian_random_field((64,) * 3, 8.0, W.SEED_GRF + p)))
+            for p in range(P_)]
+    big = W.stack_block_diagonal(mats)
+    h = amg.amg_setup(dev(big.row_ptr), dev(big.col), dev(big.val), big.grid[0], big.grid[1], big.grid[2] // P_,
+                      P_, 4096, amg.AMG_FP32)
+    b = dev(W.rhs_uniform(big.n, W.SEED_RHS + 4))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = learned.train(h, b, list(sig), degree=deg, steps=args.c4_steps, lr=3e-3, init_params=W.mlp_init(W.SEED_MLP))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"workload": "fv_diffusion_7pt_32x64^3_sigma_0.5_1_2", "degree": deg, "rows": int(big.n),
+           "levels": amg.amg_num_levels(h), "setup_s": round(setup_s, 2),
+           "train": {"steps": args.c4_steps, "s": round(train_s, 2),
+                     "ms_per_step": round(train_s / max(args.c4_steps, 1) * 1e3, 2),
+                     "loss_plain": round(res.plain_loss, 6), "loss_learned": round(res.final_loss_per_set[0], 6),
+                     "invalid_rows_last_step": res.invalid_rows}}
+    amg.amg_destroy(h)
+    del mats, big
+    held = {}
+    for i, s in enumerate((0.5, 1.0, 2.0)):
+        A = W.fv_diffusion(np.exp(s * W.gaussian_random_field((64,) * 3, 8.0, W.SEED_GRF + 900 + i)))
+        bh = dev(W.rhs_uniform(A.n, W.SEED_RHS + 60 + i))
+        hh = amg.amg_setup(dev(A.row_ptr), dev(A.col), dev(A.val), *A.grid, 1, 4096, amg.AMG_FP64)
+        lb = learned.learned_level_betas(hh, res.params, deg, s)
+        plain = learned.plain_beta(hh, deg, 1)
+        r_l, _ = learned.evaluate(hh, learned.with_level_betas(plain, lb), bh, deg, 1)
+        r_p, _ = learned.evaluate(hh, plain, bh, deg, 1)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+
+        def timed():
+            amg.pcg_solve(hh, 2, deg, bh, x, True, 1e-8, 1000)
+            torch.cuda.synchronize()
+            tm, (_, itv, _, _) = event_time(stream, lambda: amg.pcg_solve(hh, 2, deg, bh, x, True, 1e-8, 1000), 5)
+            return tm, itv
+
+        t_p, it_p = timed()
+        use = r_l < r_p
+        if use:
+            learned.apply_level_betas(hh, deg, lb)
+        t_l, it_l = timed()
+        amg.amg_reset_beta(hh)
+        held[f"sigma_{s}"] = {"two_cycle_ratio_plain": round(r_p, 6), "two_cycle_ratio_learned": round(r_l, 6),
+                              "weights": "learned" if use else "plain (fallback)",
+                              "plain_ms": round(t_p, 3), "plain_iters": it_p, "learned_ms": round(t_l, 3),
+                              "learned_iters": it_l, "learned_vs_plain": round(t_l / t_p, 3)}
+        amg.amg_destroy(hh)
+    out["heldout_solves"] = held
+    return out
+
+
 def c3_variant(amg, W, stream):
     """The 256^3 variable-coefficient diffusion problem (sigma = 1): FP64 and FP32 hierarchy,
-    optimal 4th kind, k = 4, time to 1e-8 and the difference of the two solutions."""
+    optimal 4th kind, k = 4, time to 1e-8 and the difference of the two solutions, and the
+    FP64 fine level's fused step."""
     import torch
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     t0 = time.perf_counter()
@@ -394,12 +462,15 @@ def main():
     ap.add_argument("--kind", type=int, default=2)
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--variants", default="fp32,learned,kinds,zeros,c3",
+    ap.add_argument("--variants", default="fp32,learned,kinds,zeros,c3,c4",
                     help="comma-separated subset of the variants to time: fp32 (the FP32 hierarchy), learned "
                          "(the trained network's weights), kinds (the other smoother kinds), zeros (the 27-point "
                          "operator with its stored zero entries eliminated), c3 (FP32 against FP64 on the 256^3 "
-                         "diffusion problem); empty for none")
+                         "diffusion problem), c4 (the network trained on 32 x 64^3 diffusion problems at degree "
+                         "6, held-out solves); empty for none")
     ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--c4-steps", type=int, default=100,
+                    help="Adam steps of the c4 variant (32 x 64^3 diffusion problems, degree 6)")
     ap.add_argument("--counter-sample", action="store_true",
                     help="setup, three smoother applications of degree 6 on the fine level and one 1 GiB copy "
                          "through the library's copy kernel, then exit (the program the HBM byte counters are "
@@ -539,6 +610,7 @@ def main():
     for v in variants.values():
         v["vs_plain_fp64"] = round(v["ms"] / base, 3)
     c3 = c3_variant(amg, W, stream) if "c3" in chosen else None
+    c4 = c4_variant(args, amg, W, stream) if "c4" in chosen else None
 
     # ---- CPU baseline: the oracle's smoother application on the same fine level ----
     cpu = None
@@ -566,7 +638,7 @@ def main():
                    "setup_s": round(setup_s, 3)},
         "value_frac_of_read_ceiling": round(value / ceil["read_GBps"], 4),
         "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
-        "learned": learned_info, "diffusion_256": c3,
+        "learned": learned_info, "diffusion_256": c3, "learned_32x64": c4,
     }
     print(json.dumps(out), flush=True)
 
