@@ -321,6 +321,54 @@ def test_pcg_iterations_match_oracle_32(amg, kind):
             assert relerr(host(x), ro.x) <= 1e-10
 
 
+DEGENERATE = {
+    "single_row": ((1, 1, 1), 4096),   # one unknown: the coarsest level is the whole problem
+    "tiny_2x3x1": ((2, 3, 1), 4096),   # six rows in one slice
+    "line_x": ((5000, 1, 1), 4096),    # a 1D line along x, coarsened in x only
+    "line_z": ((1, 1, 5000), 4096),    # the same line along z
+    "plane_xz": ((70, 1, 70), 1000),   # a 2D problem in the x-z plane
+    "odd_3x5x7": ((3, 5, 7), 8),       # odd extents on every level: 105 -> 24 -> 4 rows
+}
+
+
+@pytest.mark.parametrize("case", sorted(DEGENERATE))
+def test_degenerate_shapes_match_oracle(amg, case):
+    """Grids with extents of 1, a single unknown, and odd extents down to the coarsest level:
+    smoother (from x = 0 and x != 0), V-cycle and PCG against the oracle (exact counts)."""
+    torch = torch_cuda()
+    grid, mc = DEGENERATE[case]
+    A = W.poisson3d_7pt(*grid)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid, max_coarse=mc)
+    Minv = S.l1_diagonal(As)
+    rng = np.random.default_rng(12)
+    b = rng.uniform(-1, 1, A.n)
+    x0 = rng.uniform(-1, 1, A.n)
+    bd = dev(b)
+    with hierarchy(A, max_coarse=mc) as h:
+        assert amg.amg_num_levels(h) == len(H.levels), case
+        for kind in KINDS:
+            beta, a = oracle_params(kind, 3)
+            x = nan_vec(A.n)
+            amg.smoother_apply(h, 0, kind, 3, bd, x, True)
+            xd = dev(x0)
+            amg.smoother_apply(h, 0, kind, 3, bd, xd, False)
+            z = nan_vec(A.n)
+            amg.vcycle_apply(h, kind, 3, bd, z)
+            torch.cuda.synchronize()
+            assert relerr(host(x), S.smooth(As, Minv, b, None, kind, 3, beta, a)) <= TOL, (case, kind)
+            assert relerr(host(xd), S.smooth(As, Minv, b, x0, kind, 3, beta, a)) <= TOL, (case, kind)
+            assert relerr(host(z), OA.vcycle(H, b, kind, 3, beta)) <= TOL, (case, kind)
+        for kind in (2, 3):
+            beta, _ = oracle_params(kind, 4)
+            x = nan_vec(A.n)
+            rc, it, rel, _ = amg.pcg_solve(h, kind, 4, bd, x, True, 1e-8, 1000)
+            torch.cuda.synchronize()
+            ro, _ = OA.amg_pcg(As, b, A.grid, kind, 4, H=H, beta=beta)
+            assert rc == amg.AMG_OK and it == ro.iters, (case, kind, it, ro.iters)
+            assert relerr(host(x), ro.x) <= 1e-10, (case, kind)
+
+
 @pytest.mark.parametrize("kind", [1, 2, 3])
 def test_pcg_high_degrees_match_oracle(amg, kind):
     """Degrees 8..12 (the higher-degree trends of the supplement): exact PCG counts at 24^3."""
