@@ -168,6 +168,11 @@ def cpu_description():
 # ---------------------------------------------------------------------------
 # helpers on the GPU
 # ---------------------------------------------------------------------------
+def progress(msg):
+    """One line on stderr per finished part of the run (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def event_time(stream, fn, reps):
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -532,6 +537,7 @@ def main():
     M0 = lv64[0][1]
     value = solve_bytes(lv64, M0, 8, args.kind, args.degree, it, False) / (ms * 1e-3) / 1e9
 
+    progress(f"headline solves: {ms:.1f} ms, {it} iterations")
     # ---- the fine level's fused step ----
     xs = torch.zeros(n0, dtype=torch.float64, device="cuda")
     t_step = fused_step_time(amg, h, args.kind, bd, xs, stream)
@@ -539,6 +545,7 @@ def main():
     achieved = step_bytes / (t_step * 1e-3) / 1e9
     padded, lanes, aligned = amg.amg_level_layout(h, 0)
     csr_bytes = csr_model_step(nnz0, n0)
+    progress(f"fused step: {t_step * 1e3:.1f} us")
     ceil = ceiling(amg, stream)
     streams = ((n0 + 255) // 256 + 7) // 8 * 8 > STREAM_MIN_BLOCKS
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
@@ -557,6 +564,7 @@ def main():
     if traffic is not None:
         roofline["traffic"] = traffic
 
+    progress("ceiling and roofline done")
     # ---- variants ----
     chosen = {v for v in args.variants.split(",") if v}
     variants = {f"fp64_{KIND_NAMES[args.kind]}_k{args.degree}": {"ms": round(ms, 3), "iters": it}}
@@ -575,6 +583,7 @@ def main():
         tm, itv = time_solve(h, kind, args.degree)
         variants[f"fp64_{KIND_NAMES[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv,
                                                               "true_relres": true_relres(amg, h, bd, x)}
+    progress("other smoother kinds done")
     if "fp32" in chosen:
         t0 = time.perf_counter()
         h32 = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP32)
@@ -585,6 +594,7 @@ def main():
             "ms": round(tm, 3), "iters": itv, "setup_s": round(s32, 3), "outer": "FP64 flexible CG",
             "true_relres": true_relres(amg, h, bd, x)}
         amg.amg_destroy(h32)
+        progress("fp32 hierarchy done")
     if "zeros" in chosen and args.workload == "q1_27pt":
         # the same operator without its stored zero face entries (21-point pattern), as a caller
         # gets it by eliminating stored zeros: same hierarchy below the fine level, same iterates
@@ -602,15 +612,21 @@ def main():
         amg.amg_destroy(hz)
         del rpz, clz, vlz, Bz
         torch.cuda.empty_cache()
+        progress("zeros eliminated done")
     learned_info = None
     if "learned" in chosen and args.kind == 2:
         params, learned_info = train_learned(args, amg, W)
         variants[f"learned_{KIND_NAMES[args.kind]}_k{args.degree}"] = learned_variant(args, amg, W, h, bd, x,
                                                                                     stream, params)
+        progress("learned weights done")
     for v in variants.values():
         v["vs_plain_fp64"] = round(v["ms"] / base, 3)
     c3 = c3_variant(amg, W, stream) if "c3" in chosen else None
+    if c3 is not None:
+        progress("diffusion 256^3 done")
     c4 = c4_variant(args, amg, W, stream) if "c4" in chosen else None
+    if c4 is not None:
+        progress("learned 32 x 64^3 done")
 
     # ---- CPU baseline: the oracle's smoother application on the same fine level ----
     cpu = None
