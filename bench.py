@@ -501,10 +501,13 @@ def main():
     rp, cl, vl, bd = dev(A.row_ptr), dev(A.col), dev(A.val), dev(b)
     torch.cuda.synchronize()
     upload_s = time.perf_counter() - t0
+    free_before = torch.cuda.mem_get_info()[0]
     t0 = time.perf_counter()
     h = amg.amg_setup(rp, cl, vl, *A.grid, 1, 4096, amg.AMG_FP64)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    # device memory the handle holds (hierarchy, level-0 CSR copy, workspace), from the driver
+    hierarchy_bytes = free_before - torch.cuda.mem_get_info()[0]
     n0, nnz0 = amg.amg_level_info(h, 0)
     x = torch.zeros(n0, dtype=torch.float64, device="cuda")
 
@@ -651,7 +654,7 @@ def main():
         "config": {"workload": f"{args.workload}_{args.size}^3_amg_pcg_to_1e-8",
                    "smoother": KIND_NAMES[args.kind], "degree": args.degree, "n": int(n0), "nnz": int(nnz0),
                    "levels": [int(l[0]) for l in lv64], "iters": it, "assembly_s": round(assembly_s, 2), "upload_s": round(upload_s, 3),
-                   "setup_s": round(setup_s, 3)},
+                   "setup_s": round(setup_s, 3), "hierarchy_device_GB": round(hierarchy_bytes / 1e9, 2)},
         "value_frac_of_read_ceiling": round(value / ceil["read_GBps"], 4),
         "roofline": roofline, "cpu_baseline": cpu, "solve": solve_info, "variants": variants,
         "learned": learned_info, "diffusion_256": c3, "learned_32x64": c4,

@@ -110,6 +110,9 @@ typedef struct amg_opts {
                             (ties: smaller index); aggregates are numbered by root, the tentative
                             prolongator is piecewise constant (entries 1.0).  Requires nbatch = 1
                             and a structurally symmetric A; the grid extents are not used then */
+  int32_t drop_fine_csr; /* 1: free the library's CSR copy of level 0 (12 bytes per stored entry,
+                            read only by amg_level_export and amg_level_features) once setup is
+                            done; those two calls then return AMG_EINVAL for it.  0 keeps it */
 } amg_opts;
 
 /* ---------------------------------------------------------------------------
@@ -166,7 +169,9 @@ int amg_level_transfer(const amg_handle* h, int level, int* h_form, int64_t* h_s
 
 /* Copy level l's Galerkin operator (CSR, sorted columns) and its l1 inverse
  * diagonal 1/M_i into caller buffers: d_row_ptr[n+1], d_col[nnz], d_val[nnz],
- * d_minv[n] (float64).  Any pointer may be NULL to skip it.  Asynchronous. */
+ * d_minv[n] (float64).  Any pointer may be NULL to skip it.  Asynchronous.
+ * AMG_EINVAL for a level out of range, or for CSR outputs of level 0 when the handle was
+ * set up with drop_fine_csr = 1 (d_minv alone is still served). */
 int amg_level_export(const amg_handle* h, int level, int32_t* d_row_ptr, int32_t* d_col,
                      double* d_val, double* d_minv, void* stream);
 
@@ -297,7 +302,8 @@ int amg_train_loss_grad(amg_handle* h, int degree, const double* d_beta, const d
  * of d_feat (float32): degree/6, l/(nlevels-1), 1 - lambda_max(M^{-1}A_l) estimated by 20
  * power iterations from the ones vector (the margin below the l1-Jacobi bound rho <= 1),
  * (nnz_l/n_l)/27, log2(rows per problem)/24, h_sigma[p], n_{l+1}/n_l, and the mean over
- * rows of sum_{j!=i}|a_ij| / a_ii.  Synchronises. */
+ * rows of sum_{j!=i}|a_ij| / a_ii.  Synchronises.  AMG_EINVAL for a single-level handle or
+ * one set up with drop_fine_csr = 1. */
 int amg_level_features(amg_handle* h, int degree, const double* h_sigma, float* d_feat, void* stream);
 
 /* MLP 8 -> 64 -> 64 -> 6 (tanh hidden units, output scaled by 0.1), float32.

@@ -37,7 +37,8 @@ class AmgOpts(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("nbatch", ctypes.c_int32), ("max_coarse", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("agg_edge", ctypes.c_int32), ("smoothed", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
-                ("aggregation", ctypes.c_int32), ("match_steps", ctypes.c_int32), ("vbm_theta", ctypes.c_double)]
+                ("aggregation", ctypes.c_int32), ("match_steps", ctypes.c_int32), ("vbm_theta", ctypes.c_double),
+                ("drop_fine_csr", ctypes.c_int32)]
 
 
 class AmgError(RuntimeError):
@@ -140,13 +141,14 @@ def amg_strerror(code: int) -> str:
 
 
 def amg_setup(row_ptr, col, val, nx, ny, nz, nbatch=1, max_coarse=4096, precision=AMG_FP64, agg_edge=2,
-              smoothed=False, coarse_sweeps=0, aggregation=AMG_AGG_BOX, match_steps=3, vbm_theta=0.08):
+              smoothed=False, coarse_sweeps=0, aggregation=AMG_AGG_BOX, match_steps=3, vbm_theta=0.08,
+              drop_fine_csr=False):
     """Build the hierarchy for the device CSR matrix (int32 row_ptr/col, float64 val); returns the handle."""
     import torch
     n = row_ptr.numel() - 1
     nnz = col.numel()
     o = AmgOpts(nx, ny, nz, nbatch, max_coarse, precision, agg_edge, int(bool(smoothed)), coarse_sweeps,
-                aggregation, match_steps, float(vbm_theta))
+                aggregation, match_steps, float(vbm_theta), int(bool(drop_fine_csr)))
     h = ctypes.c_void_p()
     rc = lib().amg_setup(n, nnz, _ptr(row_ptr, torch.int32, name="row_ptr"), _ptr(col, torch.int32, name="col"),
                          _ptr(val, torch.float64, nnz, "val"), ctypes.byref(o), _stream(), ctypes.byref(h))

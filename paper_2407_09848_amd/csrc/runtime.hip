@@ -816,6 +816,17 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     for (int k = 1; k <= AMG_MAX_DEGREE; ++k)
       for (int j = 0; j < k; ++j) h->beta_at(l, k, j) = kOptBeta[k][j];
   AMGP_HIP(hipStreamSynchronize(s));
+  // Without export or features of level 0, its CSR copy (12 bytes per entry) is not needed
+  // once the hierarchy is built: the kernels read the sliced-ELL form.
+  if (o->drop_fine_csr) {
+    Level& L0 = h->lv[0];
+    AMGP_HIP(hipFree(L0.csr_ptr));
+    AMGP_HIP(hipFree(L0.csr_col));
+    AMGP_HIP(hipFree(L0.csr_val));
+    L0.csr_ptr = nullptr;
+    L0.csr_col = nullptr;
+    L0.csr_val = nullptr;
+  }
   return AMG_OK;
 }
 
@@ -965,6 +976,7 @@ int amg_setup(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d
   if (o.aggregation != AMG_AGG_BOX && nb != 1) return AMG_EINVAL;
   if (!(o.vbm_theta >= 0.0) || !std::isfinite(o.vbm_theta)) return AMG_EINVAL;
   if (o.match_steps < 0 || o.match_steps > 3) return AMG_EINVAL;
+  if (o.drop_fine_csr != 0 && o.drop_fine_csr != 1) return AMG_EINVAL;
   amg_handle* h = new (std::nothrow) amg_handle;
   if (!h) return AMG_ENOMEM;
   const int rc = amgp::setup(&h->impl, n, nnz, d_row_ptr, d_col, d_val, &o, (hipStream_t)stream);
@@ -1021,6 +1033,7 @@ int amg_level_export(const amg_handle* h, int level, int32_t* d_row_ptr, int32_t
                      double* d_minv, void* stream) {
   if (!h || level < 0 || level >= h->impl.nlevels) return AMG_EINVAL;
   const amgp::Level& L = h->impl.lv[level];
+  if (!L.csr_ptr && (d_row_ptr || d_col || d_val)) return AMG_EINVAL;  // dropped after setup
   hipStream_t s = (hipStream_t)stream;
   if (d_row_ptr) AMGP_HIP(hipMemcpyAsync(d_row_ptr, L.csr_ptr, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToDevice, s));
   if (d_col) AMGP_HIP(hipMemcpyAsync(d_col, L.csr_col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, s));
@@ -1196,6 +1209,8 @@ int amg_level_features(amg_handle* h, int degree, const double* h_sigma, float* 
   if (!h || !h_sigma || !d_feat || degree < 1 || degree > AMG_MAX_DEGREE) return AMG_EINVAL;
   Handle* H = &h->impl;
   if (H->nlevels < 2) return AMG_EINVAL;
+  for (int l = 0; l < H->nlevels - 1; ++l)
+    if (!H->lv[l].csr_ptr) return AMG_EINVAL;  // the level-0 CSR copy was dropped after setup
   hipStream_t s = (hipStream_t)stream;
   const int P = H->nbatch, NL = H->nlevels - 1;
   std::vector<float> feat((size_t)P * NL * 8);
@@ -1203,9 +1218,13 @@ int amg_level_features(amg_handle* h, int degree, const double* h_sigma, float* 
   double* red = nullptr;
   double* part = nullptr;
   const int64_t n0 = H->lv[0].n;
-  if (hipMalloc(&buf, sizeof(double) * 3 * n0) != hipSuccess) return AMG_ENOMEM;
-  if (hipMalloc(&red, sizeof(double) * 3 * P) != hipSuccess) return AMG_ENOMEM;
-  if (hipMalloc(&part, sizeof(double) * 64 * P) != hipSuccess) return AMG_ENOMEM;
+  if (hipMalloc(&buf, sizeof(double) * 3 * n0) != hipSuccess || hipMalloc(&red, sizeof(double) * 3 * P) != hipSuccess ||
+      hipMalloc(&part, sizeof(double) * 64 * P) != hipSuccess) {
+    hipFree(buf);
+    hipFree(red);
+    hipFree(part);
+    return AMG_ENOMEM;
+  }
   int rc = AMG_OK;
   std::vector<double> hr(3 * P);
   for (int l = 0; l < NL && rc == AMG_OK; ++l) {

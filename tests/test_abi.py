@@ -90,6 +90,36 @@ def test_argument_validation_before_device_work(L):
     # misaligned (not 16-byte) and overlapping ranges are rejected before any launch
     assert L.amg_hbm_read(P(8), 10, P(256), None) == amg.AMG_EINVAL
     assert L.amg_hbm_copy(P(256), P(272), 10, None) == amg.AMG_EINVAL
+    # an option out of range is rejected before the (here fake) device pointers are touched
+    o = amg._binding.AmgOpts(4, 4, 4, 1, 0, 0)
+    o.drop_fine_csr = 2
+    assert L.amg_setup(64, 64, P(4096), P(8192), P(16384), ctypes.byref(o), None, ctypes.byref(h)) == amg.AMG_EINVAL
+    assert not h.value
+
+
+def test_option_struct_layout_matches_the_header(tmp_path):
+    """The binding's amg_opts mirrors the C struct: same size and field offsets (a C program built
+    against include/amgpoly.h prints them)."""
+    import shutil
+    import subprocess
+
+    import paper_2407_09848_amd as amg
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in amg._binding.AmgOpts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"amgpoly.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(amg_opts));\n" +
+                   "".join(f"  printf(\"%zu\\n\", offsetof(amg_opts, {f}));\n" for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], capture_output=True,
+                       text=True)
+    assert r.returncode == 0, r.stderr
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(amg._binding.AmgOpts)
+    assert out[1:] == [getattr(amg._binding.AmgOpts, f).offset for f in fields]
 
 
 def test_product_never_imports_oracle():

@@ -177,3 +177,52 @@ def test_cg_breakdown_reports_and_keeps_x(amg):
     finally:
         torch.cuda.synchronize()
         amg.amg_destroy(h)
+
+
+def test_drop_fine_csr_frees_the_copy_and_keeps_results(amg):
+    """drop_fine_csr = 1 frees the library's level-0 CSR copy after setup (12 bytes per stored
+    entry less device memory); solves are bitwise the same, level-0 CSR export and the features
+    are refused, the l1 diagonal and the coarser levels are still exported."""
+    torch = torch_cuda()
+    A = W.q1_27pt(96)
+    b = dev(W.rhs_uniform(A.n, 51))
+    rp, cl, vl = dev(A.row_ptr), dev(A.col), dev(A.val)
+    out = {}
+    # keep, drop, keep: the first setup of the process also pays one-time runtime allocations,
+    # so the memory comparison uses the second
+    for drop in (False, True, False):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        h = amg.amg_setup(rp, cl, vl, *A.grid, drop_fine_csr=drop)
+        torch.cuda.synchronize()
+        held = free0 - torch.cuda.mem_get_info()[0]
+        try:
+            x = torch.full((A.n,), float("nan"), dtype=torch.float64, device="cuda")
+            rc, it, rel, _ = amg.pcg_solve(h, 2, 4, b, x)
+            assert rc == amg.AMG_OK
+            n1, nnz1 = amg.amg_level_info(h, 1)
+            c1 = amg.amg_level_export(h, 1)
+            mi = torch.empty(A.n, dtype=torch.float64, device="cuda")
+            assert amg._binding.lib().amg_level_export(h, 0, None, None, None, amg._binding._ptr(mi), None) == 0
+            if drop:
+                with pytest.raises(amg.AmgError) as e:
+                    amg.amg_level_export(h, 0)
+                assert e.value.code == amg.AMG_EINVAL
+                with pytest.raises(amg.AmgError) as e:
+                    amg.amg_level_features(h, 4, [0.0])
+                assert e.value.code == amg.AMG_EINVAL
+            else:
+                amg.amg_level_features(h, 4, [0.0])
+            torch.cuda.synchronize()
+            out[drop] = (held, it, rel, host(x), host(mi), [host(t) for t in c1])
+        finally:
+            torch.cuda.synchronize()
+            amg.amg_destroy(h)
+    keep, drop = out[False], out[True]
+    assert keep[1] == drop[1] and keep[2] == drop[2] and np.array_equal(keep[3], drop[3])
+    assert np.array_equal(keep[4], drop[4])
+    assert all(np.array_equal(a, c) for a, c in zip(keep[5], drop[5]))
+    saved = keep[0] - drop[0]
+    assert saved >= 0.95 * 12 * A.nnz, (keep[0], drop[0], 12 * A.nnz)
+    print(f"Q1 96^3: handle {keep[0] / 1e6:.0f} MB with the level-0 CSR copy, {drop[0] / 1e6:.0f} MB without",
+          flush=True)
