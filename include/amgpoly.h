@@ -110,9 +110,10 @@ typedef struct amg_opts {
                             (ties: smaller index); aggregates are numbered by root, the tentative
                             prolongator is piecewise constant (entries 1.0).  Requires nbatch = 1
                             and a structurally symmetric A; the grid extents are not used then */
-  int32_t drop_fine_csr; /* 1: free the library's CSR copy of level 0 (12 bytes per stored entry,
-                            read only by amg_level_export and amg_level_features) once setup is
-                            done; those two calls then return AMG_EINVAL for it.  0 keeps it */
+  int32_t drop_fine_csr; /* 1: keep no CSR form of level 0 (12 bytes per stored entry, read
+                            after setup only by amg_level_export and amg_level_features, which
+                            then return AMG_EINVAL for it): setup reads the caller's arrays in
+                            place (never writing them) instead of copying them.  0 keeps a copy */
 } amg_opts;
 
 /* ---------------------------------------------------------------------------

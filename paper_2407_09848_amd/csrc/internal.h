@@ -103,9 +103,11 @@ struct Level {
   int64_t n = 0, nnz = 0;
   int nx = 1, ny = 1, nz = 1;  // per-problem grid
   // Galerkin operator in CSR (float64), kept for export and the next Galerkin product.
+  // csr_borrowed: level 0 reads the caller's arrays during setup (not freed by the handle).
   int32_t* csr_ptr = nullptr;
   int32_t* csr_col = nullptr;
   double* csr_val = nullptr;
+  bool csr_borrowed = false;
   Ell<double> A64;
   Ell<float> A32;
   Vecs<double> v64;

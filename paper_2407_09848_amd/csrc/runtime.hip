@@ -72,9 +72,11 @@ void release(Handle* h) {
   if (h->cap) hipStreamDestroy(h->cap);
   for (size_t l = 0; l < h->lv.size(); ++l) {
     Level& L = h->lv[l];
-    hipFree(L.csr_ptr);
-    hipFree(L.csr_col);
-    hipFree(L.csr_val);
+    if (!L.csr_borrowed) {
+      hipFree(L.csr_ptr);
+      hipFree(L.csr_col);
+      hipFree(L.csr_val);
+    }
     free_ell(L.A64);
     free_ell(L.A32);
     free_vecs(L.v64, l > 0);
@@ -642,7 +644,8 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   }
   AMGP_TRY(dalloc(&h->dflag, F_NFLAG));
   AMGP_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int) * F_NFLAG, s));
-  // level 0: library-owned copy of the CSR matrix
+  // level 0: a library-owned copy of the CSR matrix, or with drop_fine_csr the caller's arrays,
+  // read (never written) until setup returns
   h->lv.emplace_back();
   {
     Level& L = h->lv.back();
@@ -651,12 +654,19 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     L.nx = o->nx;
     L.ny = o->ny;
     L.nz = o->nz;
-    AMGP_TRY(dalloc(&L.csr_ptr, n + 1));
-    AMGP_TRY(dalloc(&L.csr_col, nnz));
-    AMGP_TRY(dalloc(&L.csr_val, nnz));
-    AMGP_HIP(hipMemcpyAsync(L.csr_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
-    AMGP_HIP(hipMemcpyAsync(L.csr_col, col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
-    AMGP_HIP(hipMemcpyAsync(L.csr_val, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    if (o->drop_fine_csr) {
+      L.csr_ptr = const_cast<int32_t*>(row_ptr);
+      L.csr_col = const_cast<int32_t*>(col);
+      L.csr_val = const_cast<double*>(val);
+      L.csr_borrowed = true;
+    } else {
+      AMGP_TRY(dalloc(&L.csr_ptr, n + 1));
+      AMGP_TRY(dalloc(&L.csr_col, nnz));
+      AMGP_TRY(dalloc(&L.csr_val, nnz));
+      AMGP_HIP(hipMemcpyAsync(L.csr_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+      AMGP_HIP(hipMemcpyAsync(L.csr_col, col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+      AMGP_HIP(hipMemcpyAsync(L.csr_val, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    }
     AMGP_TRY(validate_csr(s, n, nnz, L.csr_ptr, L.csr_col, h->dflag));
   }
   for (;;) {
@@ -816,16 +826,14 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
     for (int k = 1; k <= AMG_MAX_DEGREE; ++k)
       for (int j = 0; j < k; ++j) h->beta_at(l, k, j) = kOptBeta[k][j];
   AMGP_HIP(hipStreamSynchronize(s));
-  // Without export or features of level 0, its CSR copy (12 bytes per entry) is not needed
-  // once the hierarchy is built: the kernels read the sliced-ELL form.
-  if (o->drop_fine_csr) {
+  // Without export or features of level 0 no CSR form of it is needed once the hierarchy is
+  // built (the kernels read the sliced-ELL form): forget the caller's arrays.
+  if (h->lv[0].csr_borrowed) {
     Level& L0 = h->lv[0];
-    AMGP_HIP(hipFree(L0.csr_ptr));
-    AMGP_HIP(hipFree(L0.csr_col));
-    AMGP_HIP(hipFree(L0.csr_val));
     L0.csr_ptr = nullptr;
     L0.csr_col = nullptr;
     L0.csr_val = nullptr;
+    L0.csr_borrowed = false;
   }
   return AMG_OK;
 }

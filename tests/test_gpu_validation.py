@@ -180,9 +180,10 @@ def test_cg_breakdown_reports_and_keeps_x(amg):
 
 
 def test_drop_fine_csr_frees_the_copy_and_keeps_results(amg):
-    """drop_fine_csr = 1 frees the library's level-0 CSR copy after setup (12 bytes per stored
-    entry less device memory); solves are bitwise the same, level-0 CSR export and the features
-    are refused, the l1 diagonal and the coarser levels are still exported."""
+    """drop_fine_csr = 1: setup reads the caller's CSR in place instead of copying it and keeps no
+    CSR form of level 0 (12 bytes per stored entry less device memory); solves are bitwise the
+    same, level-0 CSR export and the features are refused, the l1 diagonal and the coarser
+    levels are still exported."""
     torch = torch_cuda()
     A = W.q1_27pt(96)
     b = dev(W.rhs_uniform(A.n, 51))
@@ -191,11 +192,17 @@ def test_drop_fine_csr_frees_the_copy_and_keeps_results(amg):
     # keep, drop, keep: the first setup of the process also pays one-time runtime allocations,
     # so the memory comparison uses the second
     for drop in (False, True, False):
+        # the setup reads the caller's arrays in place with drop_fine_csr: they are left unchanged
+        # and may be freed as soon as it returns
+        rp2, cl2, vl2 = rp.clone(), cl.clone(), vl.clone()
         torch.cuda.synchronize()
         free0 = torch.cuda.mem_get_info()[0]
-        h = amg.amg_setup(rp, cl, vl, *A.grid, drop_fine_csr=drop)
+        h = amg.amg_setup(rp2, cl2, vl2, *A.grid, drop_fine_csr=drop)
         torch.cuda.synchronize()
         held = free0 - torch.cuda.mem_get_info()[0]
+        assert torch.equal(rp2, rp) and torch.equal(cl2, cl) and torch.equal(vl2, vl)
+        del rp2, cl2, vl2
+        torch.cuda.empty_cache()
         try:
             x = torch.full((A.n,), float("nan"), dtype=torch.float64, device="cuda")
             rc, it, rel, _ = amg.pcg_solve(h, 2, 4, b, x)
