@@ -185,16 +185,19 @@ def event_time(stream, fn, reps):
     return e0.elapsed_time(e1) / reps, out
 
 
-def fused_step_time(amg, h, kind, bd, xs, stream, reps=10):
+def fused_step_time(amg, h, kind, bd, xs, stream, reps=10, apply=None):
     """Average duration (ms) of the fine level's stored fused step that updates x, from smoother
     applications on level 0 from x = 0 timed with events on the launch stream.  x is updated on
     every other step, so degree 5 minus degree 4 and degree 7 minus degree 6 each add one such
     step (k_fused<...> in a kernel trace; the steps between them, which leave x alone, are
-    k_fused_keep_x)."""
+    k_fused_keep_x).  apply: the smoother entry (smoother_apply, or smoother_apply_f32 with
+    float32 vectors on an FP32 hierarchy)."""
+    apply = apply or amg.smoother_apply
+
     def time_apply(k):
         for _ in range(2):
-            amg.smoother_apply(h, 0, kind, k, bd, xs, True)
-        t, _ = event_time(stream, lambda: amg.smoother_apply(h, 0, kind, k, bd, xs, True), reps)
+            apply(h, 0, kind, k, bd, xs, True)
+        t, _ = event_time(stream, lambda: apply(h, 0, kind, k, bd, xs, True), reps)
         return t
 
     t4, t5, t6, t7 = (time_apply(k) for k in (4, 5, 6, 7))
@@ -598,6 +601,15 @@ def main():
         variants[f"fp32_{KIND_NAMES[args.kind]}_k{args.degree}"] = {
             "ms": round(tm, 3), "iters": itv, "setup_s": round(s32, 3), "outer": "FP64 flexible CG",
             "true_relres": true_relres(amg, h, bd, x)}
+        # the FP32 hierarchy's fine-level fused step (k_fused<float,...>), timed as the headline's
+        b32 = bd.float()
+        x32 = torch.zeros(n0, dtype=torch.float32, device="cuda")
+        t32 = fused_step_time(amg, h32, args.kind, b32, x32, stream, apply=amg.smoother_apply_f32)
+        step32 = fused_bytes(n0, matrix_bytes(amg, h32, 0, 4), 4, True, True)
+        variants[f"fp32_{KIND_NAMES[args.kind]}_k{args.degree}"]["fused_step"] = {
+            "avg_launch_us": round(t32 * 1e3, 2), "bytes_per_launch": int(step32),
+            "GBps": round(step32 / (t32 * 1e-3) / 1e9, 1), "frac_of_peak": round(step32 / (t32 * 1e-3) / 1e9 / PEAK_HBM, 4)}
+        del b32, x32
         amg.amg_destroy(h32)
         progress("fp32 hierarchy done")
     if "zeros" in chosen and args.workload == "q1_27pt":

@@ -211,6 +211,13 @@ int amg_spmv(amg_handle* h, int level, const double* d_x, double* d_y, void* str
 int smoother_apply(amg_handle* h, int level, int kind, int degree, const double* d_b,
                    double* d_x, int x_is_zero, void* stream);
 
+/* smoother_apply in the FP32 hierarchy (amg_opts.precision = AMG_FP32): the same recurrence on
+ * the level's float32 matrix and l1 diagonal with float32 accumulation (the smoother the FP32
+ * V-cycle applies), on float32 vectors d_b, d_x.  smoother_apply on such a handle runs the
+ * float64 copy of the level.  AMG_EINVAL also for a float64 handle. */
+int smoother_apply_f32(amg_handle* h, int level, int kind, int degree, const float* d_b, float* d_x,
+                       int x_is_zero, void* stream);
+
 /* b_c = P_l^T (b - A_l x): the restriction of the residual to level l+1 (Section 2, eq. amg),
  * computed as P_l^T b - (P_l^T A_l) x on box levels with a restriction product
  * (amg_level_transfer), else from the residual.  d_b, d_x have n_l entries, d_bc has n_{l+1}.

@@ -20,7 +20,7 @@ __all__ = [
     "amg_level_transfer", "AMG_TRANSFER_RESIDUAL", "AMG_TRANSFER_PRODUCT", "AMG_TRANSFER_EXPLICIT",
     "amg_level_export", "amg_level_aggregates", "amg_default_beta", "amg_default_astar", "amg_set_beta",
     "amg_reset_beta",
-    "amg_spmv", "smoother_apply", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
+    "amg_spmv", "smoother_apply", "smoother_apply_f32", "amg_restrict_residual", "amg_prolong_add", "amg_coarse_solve",
     "vcycle_apply", "pcg_solve", "pcg_solve_smoother", "amg_strerror", "amg_ckpt_bytes", "vcycle_fwd_ckpt", "vcycle_bwd",
     "amg_train_loss_grad", "amg_level_features", "mlp_num_params", "mlp_fwd", "mlp_bwd", "mlp_bwd_noalloc",
     "mlp_adam",
@@ -68,6 +68,7 @@ _SIGS = {
     "amg_reset_beta": (_I, [_P]),
     "amg_spmv": (_I, [_P, _I, _P, _P, _P]),
     "smoother_apply": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
+    "smoother_apply_f32": (_I, [_P, _I, _I, _I, _P, _P, _I, _P]),
     "amg_restrict_residual": (_I, [_P, _I, _P, _P, _P, _P]),
     "amg_prolong_add": (_I, [_P, _I, _P, _P, _P]),
     "amg_coarse_solve": (_I, [_P, _P, _P, _P]),
@@ -245,6 +246,15 @@ def smoother_apply(h, level, kind, degree, b, x, x_is_zero=False):
     return _check(lib().smoother_apply(h, level, kind, degree, _ptr(b, torch.float64, n, "b"),
                                        _ptr(x, torch.float64, n, "x"), int(bool(x_is_zero)), _stream()),
                   "smoother_apply")
+
+
+def smoother_apply_f32(h, level, kind, degree, b, x, x_is_zero=False):
+    """The FP32 hierarchy's smoother on float32 device vectors (an AMG_FP32 handle)."""
+    import torch
+    n, _ = amg_level_info(h, level)
+    return _check(lib().smoother_apply_f32(h, level, kind, degree, _ptr(b, torch.float32, n, "b"),
+                                           _ptr(x, torch.float32, n, "x"), int(bool(x_is_zero)), _stream()),
+                  "smoother_apply_f32")
 
 
 def amg_restrict_residual(h, level, b, x, bc):

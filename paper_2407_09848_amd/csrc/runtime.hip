@@ -1106,6 +1106,14 @@ int smoother_apply(amg_handle* h, int level, int kind, int degree, const double*
   return amgp::smooth<double>(&h->impl, level, kind, degree, d_b, d_x, x_is_zero != 0, (hipStream_t)stream);
 }
 
+int smoother_apply_f32(amg_handle* h, int level, int kind, int degree, const float* d_b, float* d_x, int x_is_zero,
+                       void* stream) {
+  if (!h || !d_b || !d_x || level < 0 || level >= h->impl.nlevels) return AMG_EINVAL;
+  if (h->impl.precision != AMG_FP32) return AMG_EINVAL;
+  AMGP_TRY(amgp::check_kind_degree(kind, degree));
+  return amgp::smooth<float>(&h->impl, level, kind, degree, d_b, d_x, x_is_zero != 0, (hipStream_t)stream);
+}
+
 int amg_restrict_residual(amg_handle* h, int level, const double* d_b, const double* d_x, double* d_bc,
                           void* stream) {
   if (!h || !d_b || !d_x || !d_bc || level < 0 || level >= h->impl.nlevels - 1) return AMG_EINVAL;

@@ -264,25 +264,48 @@ def test_fp32_hierarchy(amg):
 
 @pytest.mark.parametrize("case", ["q1_20", "fv_ragged"])
 def test_fp32_aligned_smoother(amg, case):
-    """FP32 smoother on offset-aligned fine levels, whose float values sit in step pairs with an odd
-    last step (27 and 7 offsets inside, fewer in boundary slices): every kind at degrees 1..6 stays
-    within FP32 rounding of the FP64 oracle smoother (parity unpinned: no exact FP32 answer)."""
+    """The FP32 hierarchy's smoother (smoother_apply_f32: float32 matrix, l1 diagonal, vectors and
+    accumulation) on offset-aligned fine levels, whose float values sit in quads (27-point slices)
+    or pairs (7-point) with the odd steps after them, and fewer offsets in boundary slices: every
+    kind at degrees 1..6, from x = 0 and from x != 0, stays within FP32 rounding of the FP64
+    oracle smoother (parity unpinned: no exact FP32 answer), and the float64 smoother_apply on the
+    same handle runs the float64 copy of the level (oracle bar)."""
     torch = torch_cuda()
     A = W.q1_27pt(20) if case == "q1_20" else _fv((13, 11, 9), 1.0, 6)
     As = A.to_scipy()
     Minv = S.l1_diagonal(As)
-    r = np.random.default_rng(21).uniform(-1, 1, A.n)
+    rng = np.random.default_rng(21)
+    r = rng.uniform(-1, 1, A.n)
+    x0 = rng.uniform(-1, 1, A.n)
+    r32, x032 = r.astype(np.float32), x0.astype(np.float32)
+    worst = 0.0
     with hierarchy(A, precision=amg.AMG_FP32) as h:
         _, lanes, aligned = amg.amg_level_layout(h, 0)
         assert aligned and lanes == 1
         for kind in KINDS:
             for k in range(1, 7):
-                x = nan_vec(A.n)
-                amg.smoother_apply(h, 0, kind, k, dev(r), x, True)
-                torch.cuda.synchronize()
                 beta, a = oracle_params(kind, k)
-                e = relerr(host(x), S.smooth(As, Minv, r, None, kind, k, beta, a))
-                assert e <= 1e-5, (case, kind, k, e)
+                x = torch.full((A.n,), float("nan"), dtype=torch.float32, device="cuda")
+                amg.smoother_apply_f32(h, 0, kind, k, dev(r32), x, True)
+                xd = dev(x032)
+                amg.smoother_apply_f32(h, 0, kind, k, dev(r32), xd, False)
+                x64 = nan_vec(A.n)
+                amg.smoother_apply(h, 0, kind, k, dev(r), x64, True)
+                torch.cuda.synchronize()
+                ref0 = S.smooth(As, Minv, r32.astype(np.float64), None, kind, k, beta, a)
+                ref1 = S.smooth(As, Minv, r32.astype(np.float64), x032.astype(np.float64), kind, k, beta, a)
+                e0 = relerr(host(x).astype(np.float64), ref0)
+                e1 = relerr(host(xd).astype(np.float64), ref1)
+                worst = max(worst, e0, e1)
+                assert e0 <= 5e-6 and e1 <= 5e-6, (case, kind, k, e0, e1)
+                assert relerr(host(x64), S.smooth(As, Minv, r, None, kind, k, beta, a)) <= TOL, (case, kind, k)
+        with pytest.raises(amg.AmgError):
+            amg.smoother_apply_f32(h, 0, 4, 2, dev(r32), dev(x032), False)
+    with hierarchy(A) as h64:
+        with pytest.raises(amg.AmgError) as e:
+            amg.smoother_apply_f32(h64, 0, 2, 2, dev(r32), dev(x032), False)
+        assert e.value.code == amg.AMG_EINVAL
+    print(f"FP32 smoother on {case}: largest error against the FP64 oracle {worst:.2e}", flush=True)
 
 
 def test_vcycle_full_size_c2(amg):
