@@ -23,7 +23,9 @@ from oracle import amg as OA  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-NCASES = 160
+# 160 seeded cases by default; AMGP_SWEEP_FIRST / AMGP_SWEEP_CASES select another range of seeds
+FIRST = int(os.environ.get("AMGP_SWEEP_FIRST", "0"))
+NCASES = int(os.environ.get("AMGP_SWEEP_CASES", "160"))
 
 
 @pytest.fixture(scope="module")
@@ -84,7 +86,7 @@ def _lib_opts(amg, agg, opts):
     return o
 
 
-@pytest.mark.parametrize("seed", range(NCASES))
+@pytest.mark.parametrize("seed", range(FIRST, FIRST + NCASES))
 def test_sweep_case_matches_oracle(amg, seed):
     torch = torch_cuda()
     fam, A, agg, opts, mc, kinds, degs = _case(seed)
