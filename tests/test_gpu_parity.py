@@ -308,6 +308,29 @@ def test_fp32_aligned_smoother(amg, case):
     print(f"FP32 smoother on {case}: largest error against the FP64 oracle {worst:.2e}", flush=True)
 
 
+def test_fp32_smoother_every_level(amg):
+    """smoother_apply_f32 on every level of an FP32 box hierarchy of the 27-point problem (the
+    offset-aligned fine level, the four-lane packed coarse levels and the coarsest level) against
+    the FP64 oracle smoother on the oracle's level operator, within FP32 rounding."""
+    torch = torch_cuda()
+    A = W.q1_27pt(26, 22, 18)
+    H = OA.build_hierarchy(A.to_scipy(), A.grid, max_coarse=60)
+    rng = np.random.default_rng(23)
+    with hierarchy(A, max_coarse=60, precision=amg.AMG_FP32) as h:
+        assert amg.amg_num_levels(h) == len(H.levels) >= 4
+        for l, lv in enumerate(H.levels):
+            n = lv.A.shape[0]
+            b32 = rng.uniform(-1, 1, n).astype(np.float32)
+            for kind, k in ((0, 3), (1, 4), (2, 5), (3, 6)):
+                beta, a = oracle_params(kind, k)
+                x = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+                amg.smoother_apply_f32(h, l, kind, k, dev(b32), x, True)
+                torch.cuda.synchronize()
+                ref = S.smooth(lv.A, lv.Minv, b32.astype(np.float64), None, kind, k, beta, a)
+                e = relerr(host(x).astype(np.float64), ref)
+                assert e <= 5e-6, (l, n, kind, k, e)
+
+
 def test_vcycle_full_size_c2(amg):
     """128^3 7-point Poisson, optimal 4th kind k = 4: the whole V-cycle output vs the oracle."""
     torch = torch_cuda()
