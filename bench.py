@@ -10,7 +10,7 @@ in HBM (setup excluded, reported separately).  A step is one such solve.
 value        = bytes one solve must move in the storage layouts the kernels use
                (summed from the per-kernel models below over the launches of one
                solve) / the solve's wall time, GB/s;
-roofline     = the fine-level fused recurrence step (k_fused<double,0,true,true,1>):
+roofline     = the fine-level fused recurrence step (k_fused<double,0,true,true,1,true>):
                the bytes it must move per launch / its average duration, timed
                here with events on the launch stream (degree-5 minus degree-4
                and degree-7 minus degree-6 smoother applications from x = 0,
@@ -51,6 +51,7 @@ PEAK_HBM = 8000.0  # GB/s, MI355X HBM3E
 KIND_NAMES = {0: "l1jacobi", 1: "cheb4", 2: "optcheb4", 3: "optcheb1"}
 FUSED_PROLONG_MAX_ROWS = 1 << 20  # box levels up to this size carry the prolongation in the smoother
 STREAM_MIN_BLOCKS = 12288  # levels above this many 256-row blocks take the streaming kernels
+WIDE_MIN_STEPS = 24  # streaming offset-aligned levels with this many stored steps per row take wide batches
 
 
 # ---------------------------------------------------------------------------
@@ -556,10 +557,12 @@ def main():
     progress(f"fused step: {t_step * 1e3:.1f} us")
     ceil = ceiling(amg, stream)
     streams = ((n0 + 255) // 256 + 7) // 8 * 8 > STREAM_MIN_BLOCKS
+    # wide slices (at least 24 stored steps per row on average) take the wide-batch variant
+    wide = streams and aligned and lanes == 1 and padded >= WIDE_MIN_STEPS * n0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
-                "kernel": f"k_fused<double,0,true,{str(streams).lower()},1> (fine level, {args.workload} "
-                          f"{args.size}^3)",
+                "kernel": f"k_fused<double,0,true,{str(streams).lower()},1,{str(wide).lower()}> (fine level, "
+                          f"{args.workload} {args.size}^3)",
                 "bytes_per_launch": int(step_bytes), "avg_launch_us": round(t_step * 1e3, 2),
                 "layout": {"stored_entries": int(padded), "lanes_per_row": lanes, "offset_aligned": aligned,
                            "bytes_per_launch": "8 per stored entry + 4 per 64 + 56 per row"},

@@ -207,12 +207,21 @@ __device__ __forceinline__ float aligned_sum_f32(const float* __restrict__ val, 
 // 7-point level at 256^3 0.296 ms (batches of 8: 0.305; unpaired: 0.319).
 constexpr int kAlignedBatch = 6;
 
+// Wide slices (levels averaging at least kWideMinSteps steps per row: the 27-point ones) take
+// batches of kWideBatch steps, six 16-byte loads per lane, and their kernels request the row's
+// own vectors before the product.  Measured on the fused step of a synthetic 27-point level of
+// 32.8M rows (three runs each): 1620-1621 us against 1651-1652 us for batches of 6 with the row
+// vectors after the product; batches of 12 alone: 1631 us.  Seven-step slices never fill a
+// batch of 12 (299 against 320-336 us), so narrower levels keep batches of 6.
+constexpr int kWideBatch = 12;
+constexpr int kWideMinSteps = 2 * kWideBatch;
+
 // Batched = false: one pair per iteration (rows of a wavefront in different slices, where the
 // batches would diverge).
-template <bool NT, typename Gf, bool Batched = true>
+template <bool NT, typename Gf, bool Batched = true, int B = kAlignedBatch>
 __device__ __forceinline__ double aligned_sum_f64(const double* __restrict__ val, int beg, int end, int lane,
                                                   const int32_t* __restrict__ off, int r, int last, Gf g) {
-  constexpr int B = kAlignedBatch, H = kAlignedBatch / 2;
+  constexpr int H = B / 2;
   const int w = (end - beg) >> 6;
   const int wp = w & ~1;
   const int nb = Batched ? wp / B : 0;
@@ -266,8 +275,9 @@ __device__ __forceinline__ bool exit_rows(int64_t i, int64_t n) {
   return (logical_block() * kBlock + (threadIdx.x & ~(kWave - 1))) / G >= n;
 }
 
-// (A x)_row; with G > 1 every lane of the row's group returns the sum.
-template <bool NT, int G, typename T>
+// (A x)_row; with G > 1 every lane of the row's group returns the sum.  AB: the batch of the
+// FP64 offset-aligned sum.
+template <bool NT, int G, int AB = kAlignedBatch, typename T>
 __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restrict__ x) {
   constexpr int R = kSlice / G;
   // every lane of the wavefront is in the same slice: read its bounds once, as scalars
@@ -283,7 +293,8 @@ __device__ __forceinline__ T ell_dot(EllView<T> A, int64_t row, const T* __restr
     if constexpr (std::is_same_v<T, float>) {
       return aligned_sum_f32<NT>(A.val, beg, end, lane, off, r, A.last, [&](int c) { return x[c]; });
     } else {
-      return aligned_sum_f64<NT>(A.val, beg, end, lane, off, r, A.last, [&](int c) { return x[c]; });
+      auto g = [&](int c) { return x[c]; };
+      return aligned_sum_f64<NT, decltype(g), true, AB>(A.val, beg, end, lane, off, r, A.last, g);
     }
   }
 #pragma unroll 4
@@ -356,23 +367,34 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 // both directions, which it reads anyway, in the same order).
 // STORE = false on the last step of an application: only x is needed.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool STORE, bool NT, int G, bool XUPD>
+// W: wide slices (one row per lane): the row's vectors are requested before the product, whose
+// steps go in batches of kWideBatch.
+template <typename T, int MODE, bool STORE, bool NT, int G, bool XUPD, bool W>
 __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                           const T* __restrict__ gold, T* __restrict__ gnew, const T* rin, T* rout,
                                           T* __restrict__ x, T alpha, T c, T w, T wprev, Wt wv, Wt wpv, Prol<T> pr) {
   const int64_t i = row_of_thread<G>();
   if (exit_rows<G>(i, n)) return;
-  const T ag = ell_dot<NT, G>(A, i, gold);
+  T mi, go, ri, xi = T(0);
+  if constexpr (W) {
+    mi = ld<NT>(minv + i);
+    go = gold[i];
+    ri = ld<NT>(rin + i);
+    if constexpr (XUPD) xi = ld<NT>(x + i);
+  }
+  const T ag = ell_dot<NT, G, W ? kWideBatch : kAlignedBatch>(A, i, gold);
   if (!row_owner<G>(i, n)) return;
-  const T mi = ld<NT>(minv + i);
-  const T go = gold[i];
-  const T ri = ld<NT>(rin + i);
+  if constexpr (!W) {
+    mi = ld<NT>(minv + i);
+    go = gold[i];
+    ri = ld<NT>(rin + i);
+  }
   const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
   if constexpr (XUPD) {
     w = wsel(wv, w, i);
     wprev = wsel(wpv, wprev, i);
-    T xi = ld<NT>(x + i);
+    if constexpr (!W) xi = ld<NT>(x + i);
     if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
     st<NT>(x + i, xi + wprev * go + w * g);
   }
@@ -382,22 +404,22 @@ __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __r
   }
 }
 
-template <typename T, int MODE, bool STORE, bool NT, int G>
+template <typename T, int MODE, bool STORE, bool NT, int G, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_fused(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                   const T* __restrict__ gold, T* __restrict__ gnew,
                                                   const T* rin, T* rout, T* __restrict__ x, T alpha, T c, T w,
                                                   T wprev, Wt wv, Wt wpv, Prol<T> pr) {
-  fused_step<T, MODE, STORE, NT, G, true>(n, A, minv, gold, gnew, rin, rout, x, alpha, c, w, wprev, wv, wpv, pr);
+  fused_step<T, MODE, STORE, NT, G, true, W>(n, A, minv, gold, gnew, rin, rout, x, alpha, c, w, wprev, wv, wpv, pr);
 }
 
 // A stored step that leaves x alone: the next step adds this step's weighted direction (which it
 // reads anyway as its own old direction) together with its own.
-template <typename T, int MODE, bool NT, int G>
+template <typename T, int MODE, bool NT, int G, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_fused_keep_x(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                          const T* __restrict__ gold, T* __restrict__ gnew,
                                                          const T* rin, T* rout, T alpha, T c) {
-  fused_step<T, MODE, true, NT, G, false>(n, A, minv, gold, gnew, rin, rout, nullptr, alpha, c, T(0), T(0), Wt(),
-                                          Wt(), Prol<T>());
+  fused_step<T, MODE, true, NT, G, false, W>(n, A, minv, gold, gnew, rin, rout, nullptr, alpha, c, T(0), T(0), Wt(),
+                                             Wt(), Prol<T>());
 }
 
 // END fused-step
@@ -434,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __res
 // vectors disappears.
 // MODE 0: g1 = c1 M^{-1} b, r1 = b - A g1, g2 = alpha g1 + c M^{-1} r1, x = w1 g1 + w2 g2.
 // MODE 1: r0 = M^{-1} b, d0 = r0 / theta, r1 = r0 - M^{-1} A d0, d1 = alpha d0 + c r1, x = d0 + d1.
-template <typename T, int MODE, bool STORE, bool NT, int G>
+template <typename T, int MODE, bool STORE, bool NT, int G, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                         const T* __restrict__ b, T* __restrict__ gnew,
                                                         T* __restrict__ r, T* __restrict__ x, T c1, T alpha, T c,
@@ -446,17 +468,20 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
   const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
   const int lane = G == 1 ? (int)(i & 63) : (int)(threadIdx.x & 63);
+  T mi = T(0), bi = T(0);
+  if constexpr (W) {  // wide slices: the row's own entries first (see kWideBatch)
+    mi = minv[i];
+    bi = b[i];
+  }
   T ag = T(0);
   if (G == 1 && A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
+    auto g1 = [&](int j) { return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1; };
     if constexpr (std::is_same_v<T, float>) {
-      ag = aligned_sum_f32<NT>(A.val, beg, end, lane, off, (int)i, A.last, [&](int j) {
-        return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-      });
+      ag = aligned_sum_f32<NT>(A.val, beg, end, lane, off, (int)i, A.last, g1);
     } else {
-      ag = aligned_sum_f64<NT>(A.val, beg, end, lane, off, (int)i, A.last, [&](int j) {
-        return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-      });
+      ag = aligned_sum_f64<NT, decltype(g1), true, W ? kWideBatch : kAlignedBatch>(A.val, beg, end, lane, off, (int)i,
+                                                                                    A.last, g1);
     }
   } else {
 #pragma unroll 4
@@ -472,8 +497,10 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
   if (!row_owner<G>(i, n)) return;
   w1 = wsel(w1v, w1, i);
   w2 = wsel(w2v, w2, i);
-  const T mi = minv[i];
-  const T bi = b[i];
+  if constexpr (!W) {
+    mi = minv[i];
+    bi = b[i];
+  }
   T g1, r1, g2;
   if (MODE == 0) {
     g1 = c1 * (mi * bi);
@@ -496,16 +523,24 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
 // First step from a nonzero x: r^(0) from b - A x.  x is gathered here, so its
 // update is deferred to the next step (or a separate axpy when k = 1).
 // MODE 0: r = b - A x, g = c M^{-1} r.   MODE 1: r = M^{-1}(b - A x), g = r / c (c = theta).
-template <typename T, int MODE, bool NT, int G>
+template <typename T, int MODE, bool NT, int G, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                       const T* __restrict__ b, const T* __restrict__ x,
                                                       T* __restrict__ r, T* __restrict__ g, T c) {
   const int64_t i = row_of_thread<G>();
   if (exit_rows<G>(i, n)) return;
-  const T ax = ell_dot<NT, G>(A, i, x);
+  T bi = T(0), mi = T(0);
+  if constexpr (W) {  // wide slices: the row's own entries first (see kWideBatch)
+    bi = ld<NT>(b + i);
+    mi = ld<NT>(minv + i);
+  }
+  const T ax = ell_dot<NT, G, W ? kWideBatch : kAlignedBatch>(A, i, x);
   if (!row_owner<G>(i, n)) return;
-  const T res = ld<NT>(b + i) - ax;
-  const T mi = ld<NT>(minv + i);
+  if constexpr (!W) {
+    bi = ld<NT>(b + i);
+    mi = ld<NT>(minv + i);
+  }
+  const T res = bi - ax;
   if (MODE == 0) {
     st<NT>(r + i, res);
     g[i] = c * (mi * res);
@@ -773,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __rest
 // instead of two (measured on a 27-point level of 32.8M rows: 1.36 ms + 0.13 ms for the separate
 // pass, against 1.77 ms with z and p_old both gathered; 7-point 256^3: 0.191 + 0.071 against
 // 0.284 ms).  The values and the products are the same either way.
-template <bool NT, typename TZ, bool PRE>
+template <bool NT, typename TZ, bool PRE, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double> A, const double* __restrict__ scal,
                                                        const TZ* __restrict__ z, const double* __restrict__ pold,
                                                        double* pnew, double* __restrict__ q,
@@ -792,10 +827,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     const int s = __builtin_amdgcn_readfirstlane((int)(i >> 6));
     const int beg = __builtin_amdgcn_readfirstlane(A.sptr[s]);
     const int end = __builtin_amdgcn_readfirstlane(A.sptr[s + 1]);
+    double pw = 0.0;
+    if constexpr (PRE && W) pw = pnew[i];  // wide slices: the row's own entry first (see kWideBatch)
     double acc = 0.0;
     if (A.doff) {
       const int32_t* off = A.doff + (beg >> 6);
-      acc = aligned_sum_f64<kStreamVal>(A.val, beg, end, (int)(i & 63), off, (int)i, A.last, pj);
+      acc = aligned_sum_f64<kStreamVal, decltype(pj), true, W ? kWideBatch : kAlignedBatch>(
+          A.val, beg, end, (int)(i & 63), off, (int)i, A.last, pj);
     } else {
 #pragma unroll 4
       for (int p = beg + (int)(i & 63); p < end; p += kSlice) {
@@ -805,7 +843,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     }
     double pi;
     if constexpr (PRE) {
-      pi = pnew[i];
+      pi = W ? pw : pnew[i];
     } else {
       pi = z[i] + beta * pold[i];
       st<NT>(pnew + i, pi);
@@ -958,6 +996,13 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(int64_t n, const double
 // Levels above kRemapMaxBlocks blocks take the streaming (NT) kernels (one row per lane).
 inline bool streamed(unsigned grid) { return grid > kRemapMaxBlocks; }
 
+// FP64 offset-aligned levels of one row per lane averaging at least kWideMinSteps stored steps
+// per row take the wide-batch kernels (W = true); FP32 levels keep theirs (quads in batches of
+// 12 steps already).
+inline bool wide(const Ell<double>& A) {
+  return A.doff && A.group == 1 && A.padded >= (int64_t)kWideMinSteps * A.n;
+}
+
 // Runs f(std::integral_constant<int, G>) for the matrix's lanes per row G.
 template <typename F>
 int with_group(int group, F&& f) {
@@ -1026,22 +1071,22 @@ int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* m
   return LAUNCH_OK();
 }
 
-template <typename T, bool NT, int G>
+template <typename T, bool NT, int G, bool W = false>
 void go_first2_zero(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv,
                     const T* b, T* gnew, T* r, T* x, T a1, T a2, T a3, T a4, T a5, Wt w1v, Wt w2v) {
   dim3 bl(kBlock);
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
-                       a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
+                       a4, a5, w1v, w2v);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
-                       a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
+                       a4, a5, w1v, w2v);
   else if (store)
-    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
-                       a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
+                       a4, a5, w1v, w2v);
   else
-    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT, G>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3, a4,
-                       a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
+                       a4, a5, w1v, w2v);
 }
 
 template <typename T>
@@ -1052,6 +1097,13 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
     const dim3 gr(xcd_grid(A.n * G));
     if constexpr (G == 1) {
       if (streamed(gr.x)) {
+        if constexpr (std::is_same_v<T, double>) {
+          if (wide(A)) {
+            go_first2_zero<T, true, 1, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha,
+                                             (T)c, (T)w1, (T)w2, w1v, w2v);
+            return;
+          }
+        }
         go_first2_zero<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c,
                                    (T)w1, (T)w2, w1v, w2v);
         return;
@@ -1062,13 +1114,13 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
   });
 }
 
-template <typename T, bool NT, int G>
+template <typename T, bool NT, int G, bool W = false>
 void go_first_res(dim3 gr, hipStream_t s, int mode, EllView<T> A, int64_t n, const T* minv, const T* b, const T* x,
                   T* r, T* g, T c) {
   if (mode == 0)
-    hipLaunchKernelGGL((k_first_res<T, 0, NT, G>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
+    hipLaunchKernelGGL((k_first_res<T, 0, NT, G, W>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
   else
-    hipLaunchKernelGGL((k_first_res<T, 1, NT, G>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
+    hipLaunchKernelGGL((k_first_res<T, 1, NT, G, W>), gr, dim3(kBlock), 0, s, n, A, minv, b, x, r, g, c);
 }
 
 template <typename T>
@@ -1098,6 +1150,12 @@ int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, co
     const dim3 gr(xcd_grid(A.n * G));
     if constexpr (G == 1) {
       if (streamed(gr.x)) {
+        if constexpr (std::is_same_v<T, double>) {
+          if (wide(A)) {
+            go_first_res<T, true, 1, true>(gr, s, mode, view(A), A.n, minv, b, x, r, g, (T)c);
+            return;
+          }
+        }
         go_first_res<T, true, 1>(gr, s, mode, view(A), A.n, minv, b, x, r, g, (T)c);
         return;
       }
@@ -1106,29 +1164,29 @@ int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, co
   });
 }
 
-template <typename T, bool NT, int G>
+template <typename T, bool NT, int G, bool W = false>
 void go_fused(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv, const T* gold,
               T* gnew, const T* rin, T* rout, T* x, T a_, T c_, T w_, T wp_, Wt wv, Wt wpv, Prol<T> pr) {
   dim3 bl(kBlock);
   if (!x) {  // a stored step that leaves x alone (the caller only passes null x with store set)
     if (mode == 0)
-      hipLaunchKernelGGL((k_fused_keep_x<T, 0, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
+      hipLaunchKernelGGL((k_fused_keep_x<T, 0, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
     else
-      hipLaunchKernelGGL((k_fused_keep_x<T, 1, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
+      hipLaunchKernelGGL((k_fused_keep_x<T, 1, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, a_, c_);
     return;
   }
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_fused<T, 0, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv, pr);
+    hipLaunchKernelGGL((k_fused<T, 0, true, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_, wv, wpv, pr);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_fused<T, 0, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv, pr);
+    hipLaunchKernelGGL((k_fused<T, 0, false, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_, wv, wpv, pr);
   else if (store)
-    hipLaunchKernelGGL((k_fused<T, 1, true, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv, pr);
+    hipLaunchKernelGGL((k_fused<T, 1, true, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_, wv, wpv, pr);
   else
-    hipLaunchKernelGGL((k_fused<T, 1, false, NT, G>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_, w_,
-                       wp_, wv, wpv, pr);
+    hipLaunchKernelGGL((k_fused<T, 1, false, NT, G, W>), gr, bl, 0, s, n, A, minv, gold, gnew, rin, rout, x, a_, c_,
+                       w_, wp_, wv, wpv, pr);
 }
 
 template <typename T>
@@ -1140,6 +1198,13 @@ int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* 
     const dim3 gr(xcd_grid(A.n * G));
     if constexpr (G == 1) {
       if (streamed(gr.x)) {
+        if constexpr (std::is_same_v<T, double>) {
+          if (wide(A)) {
+            go_fused<T, true, 1, true>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha,
+                                       (T)c, (T)w, (T)wprev, wv, wpv, pr);
+            return;
+          }
+        }
         go_fused<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
                              (T)wprev, wv, wpv, pr);
         return;
@@ -1265,8 +1330,12 @@ int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, c
   const unsigned g = xcd_grid(A.n);
   if (streamed(g)) {
     hipLaunchKernelGGL((k_form_p<true, TZ>), dim3(g), dim3(kBlock), 0, s, A.n, scal, z, pold, pnew);
-    hipLaunchKernelGGL((k_spmv_dot_p<true, TZ, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold, pnew,
-                       q, partial);
+    if (wide(A))
+      hipLaunchKernelGGL((k_spmv_dot_p<true, TZ, true, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z,
+                         pold, pnew, q, partial);
+    else
+      hipLaunchKernelGGL((k_spmv_dot_p<true, TZ, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold,
+                         pnew, q, partial);
   } else {
     hipLaunchKernelGGL((k_spmv_dot_p<false, TZ, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold,
                        pnew, q, partial);
