@@ -80,6 +80,15 @@ __device__ __forceinline__ void st(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
+// The row's l1 inverse diagonal, read by every step of a level: an ordinary load on wide
+// (27-point) FP64 levels and on FP32 levels, a nontemporal one on the other streaming FP64
+// levels.  Measured: 320^3 27-point solve 482.5 -> 480.5 ms, the 256^3 diffusion solve with the
+// FP32 hierarchy 61.2 -> 60.7 ms; on the 7-point FP64 level ordinary loads cost 5% (294 -> 310 us).
+template <bool NT, bool W, typename T>
+__device__ __forceinline__ T ld_minv(const T* p) {
+  if constexpr (W || std::is_same_v<T, float>) return *p; else return ld<NT>(p);
+}
+
 // Offset-aligned slices keep each lane's steps in pairs: steps 2q and 2q + 1 of lane l sit at
 // 128 q + 2 l and 128 q + 2 l + 1 of the slice (an odd last step t at 64 t + l), so one load per
 // lane serves two steps: 16 bytes in FP64 (a wavefront load is 1 KB contiguous), 8 in FP32.
@@ -377,7 +386,7 @@ __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __r
   if (exit_rows<G>(i, n)) return;
   T mi, go, ri, xi = T(0);
   if constexpr (W) {
-    mi = ld<NT>(minv + i);
+    mi = ld_minv<NT, W>(minv + i);
     go = gold[i];
     ri = ld<NT>(rin + i);
     if constexpr (XUPD) xi = ld<NT>(x + i);
@@ -385,7 +394,7 @@ __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __r
   const T ag = ell_dot<NT, G, W ? kWideBatch : kAlignedBatch>(A, i, gold);
   if (!row_owner<G>(i, n)) return;
   if constexpr (!W) {
-    mi = ld<NT>(minv + i);
+    mi = ld_minv<NT, W>(minv + i);
     go = gold[i];
     ri = ld<NT>(rin + i);
   }
@@ -532,13 +541,13 @@ __global__ __launch_bounds__(kBlock) void k_first_res(int64_t n, EllView<T> A, c
   T bi = T(0), mi = T(0);
   if constexpr (W) {  // wide slices: the row's own entries first (see kWideBatch)
     bi = ld<NT>(b + i);
-    mi = ld<NT>(minv + i);
+    mi = ld_minv<NT, W>(minv + i);
   }
   const T ax = ell_dot<NT, G, W ? kWideBatch : kAlignedBatch>(A, i, x);
   if (!row_owner<G>(i, n)) return;
   if constexpr (!W) {
     bi = ld<NT>(b + i);
-    mi = ld<NT>(minv + i);
+    mi = ld_minv<NT, W>(minv + i);
   }
   const T res = bi - ax;
   if (MODE == 0) {
