@@ -417,6 +417,19 @@ void free_adj(std::vector<AdjVecs<T>>& adj) {
   adj.clear();
 }
 
+void train_release(Handle* h) {
+  free_adj(h->adj64);
+  free_adj(h->adj32);
+  hipFree(h->tr_buf);
+  hipFree(h->tr_sq);
+  hipFree(h->tr_loss);
+  hipFree(h->tr_partial);
+  h->tr_buf = nullptr;
+  h->tr_sq = nullptr;
+  h->tr_loss = nullptr;
+  h->tr_partial = nullptr;
+}
+
 int train_prepare(Handle* h) {
   if (h->train_ready) return AMG_OK;
   h->ck_off.assign(h->nlevels, 0);
@@ -426,18 +439,22 @@ int train_prepare(Handle* h) {
     off += 2 * h->lv[l].n;
   }
   h->ck_count = off;
-  if (h->precision == AMG_FP32)
-    AMGP_TRY(alloc_adj<float>(h, h->adj32));
-  else
-    AMGP_TRY(alloc_adj<double>(h, h->adj64));
   const size_t w = h->precision == AMG_FP32 ? sizeof(float) : sizeof(double);
   const int64_t n0 = h->lv[0].n;
+  int rc = h->precision == AMG_FP32 ? alloc_adj<float>(h, h->adj32) : alloc_adj<double>(h, h->adj64);
   // driver: r0, z, r1, r2, g, t (6 x n0) + two checkpoints
-  if (hipMalloc(&h->tr_buf, w * (size_t)(6 * n0 + 2 * std::max<int64_t>(h->ck_count, 1))) != hipSuccess)
-    return AMG_ENOMEM;
-  AMGP_TRY(dalloc(&h->tr_sq, 2 * h->nbatch));
-  AMGP_TRY(dalloc(&h->tr_loss, 1 + h->nbatch));
-  AMGP_TRY(dalloc(&h->tr_partial, 64 * (int64_t)std::max(2 * h->nbatch, 8)));
+  if (rc == AMG_OK &&
+      hipMalloc(&h->tr_buf, w * (size_t)(6 * n0 + 2 * std::max<int64_t>(h->ck_count, 1))) != hipSuccess) {
+    h->tr_buf = nullptr;
+    rc = AMG_ENOMEM;
+  }
+  if (rc == AMG_OK) rc = dalloc(&h->tr_sq, 2 * h->nbatch);
+  if (rc == AMG_OK) rc = dalloc(&h->tr_loss, 1 + h->nbatch);
+  if (rc == AMG_OK) rc = dalloc(&h->tr_partial, 64 * (int64_t)std::max(2 * h->nbatch, 8));
+  if (rc != AMG_OK) {  // nothing half-allocated is kept: a later call starts over
+    train_release(h);
+    return rc;
+  }
   h->train_ready = true;
   return AMG_OK;
 }
