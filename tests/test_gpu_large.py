@@ -6,6 +6,9 @@ At these sizes the oracle cannot run a whole solve in a test, so:
   value at row i depends only on rows within grid distance k of i, so the
   oracle recurrence on the radius-k sub-grid around i (with M^{-1} taken from
   the full rows) reproduces it exactly;
+* whole vectors are compared with the oracle where one oracle application runs in seconds
+  (the 320^3 fine level's smoothers and restriction, and at 256^3 the smoothers, the
+  restriction and a V-cycle through the oracle's whole hierarchy);
 * CG solutions are checked through properties that hold at any size: the
   true residual ||b - A x|| / ||b|| computed by the oracle's SpMV, and the
   FP32-hierarchy solve against the FP64 one.
@@ -222,6 +225,48 @@ def test_c3_fp32_vs_fp64_full_size():
     e = np.linalg.norm(xs[amg.AMG_FP32] - xs[amg.AMG_FP64]) / np.linalg.norm(xs[amg.AMG_FP64])
     _log(f"C3 FP32-hierarchy solution vs FP64: relative difference {e:.2e}")
     assert e <= 1e-6
+
+
+def test_c3_fp64_full_vectors():
+    """The 256^3 diffusion problem's FP64 hierarchy (16.8M-row fine level on the streaming kernels,
+    7 stored steps per row) against the oracle on every entry: one application of each smoother
+    kind at degree 4 from x = 0, the restriction of a random x, and one V-cycle (optimal 4th kind,
+    k = 4) through the oracle's whole hierarchy."""
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    from oracle import amg as OA
+    A, b, _ = W.config_problem(3)
+    As = A.to_scipy()
+    Minv = S.l1_diagonal(As)
+    bd = dev(b)
+    with hierarchy(A) as h:
+        for kind in (0, 1, 2, 3):
+            x = nan_vec(A.n)
+            amg.smoother_apply(h, 0, kind, 4, bd, x, True)
+            torch.cuda.synchronize()
+            beta, a = oracle_params(kind, 4)
+            e = relerr(host(x), S.smooth(As, Minv, b, None, kind, 4, beta, a))
+            _log(f"C3 full-vector smoother kind {kind}, k = 4: {e:.2e}")
+            assert e <= 1e-12, (kind, e)
+        agg, cgrid = OA.box_aggregates(A.grid)
+        nc = int(np.prod(cgrid))
+        xr = np.random.default_rng(22).uniform(-1, 1, A.n)
+        bc = nan_vec(nc)
+        amg.amg_restrict_residual(h, 0, bd, dev(xr), bc)
+        torch.cuda.synchronize()
+        e = relerr(host(bc), OA.prolongator(agg, nc).T @ (b - As @ xr))
+        _log(f"C3 full-vector restriction ({nc} aggregates): {e:.2e}")
+        assert e <= 1e-13, e
+        t = time.time()
+        H = OA.build_hierarchy(As, A.grid)
+        _log(f"C3 oracle hierarchy in {time.time() - t:.0f} s")
+        assert amg.amg_num_levels(h) == len(H.levels)
+        z = nan_vec(A.n)
+        amg.vcycle_apply(h, 2, 4, bd, z)
+        torch.cuda.synchronize()
+        e = relerr(host(z), OA.vcycle(H, b, 2, 4))
+        _log(f"C3 full-vector V-cycle (optimal 4th kind, k = 4): {e:.2e}")
+        assert e <= 1e-12, e
 
 
 def test_aniso_full_size():
