@@ -183,10 +183,12 @@ __global__ __launch_bounds__(256) void k_pack_tiles(int64_t np, int ntiles, cons
 // in registers).  The 64-vectors land in part[p][row block][column block]; a
 // second kernel sums them in a fixed order.  b and x are level vectors (nl rows
 // per problem); padding rows read as 0.
-template <typename T>
+// RB: rows of the tile transposed through LDS at a time (RB x (TM + 1) doubles of LDS per
+// wavefront); every row sum still adds its 64 products in column order.
+template <typename T, int RB = TM>
 __global__ __launch_bounds__(TM) void k_symv_tiles(int nb, int ntiles, int64_t nl, const double* __restrict__ packed,
                                                    const T* __restrict__ b, double* __restrict__ part) {
-  __shared__ double prod[TM][TM + 1];
+  __shared__ double prod[RB][TM + 1];
   const int q = blockIdx.x, p = blockIdx.y, lane = threadIdx.x;
   int J, I;
   tile_of(q, J, I);
@@ -195,20 +197,24 @@ __global__ __launch_bounds__(TM) void k_symv_tiles(int nb, int ntiles, int64_t n
   const double bI = ri < nl ? (double)bp[ri] : 0.0;
   const double bJ = rj < nl ? (double)bp[rj] : 0.0;
   const double* src = packed + ((int64_t)p * ntiles + q) * TM * TM + lane;
-  double col = 0.0;
+  double col = 0.0, row = 0.0;
   // the tiles (67 MB at 4096 rows) are read once per cycle with streaming loads, so that they do
   // not displace the fine level's matrix and vectors from the caches (measured at 128^3: 18.3 to
   // 16.2 us here, and the whole PCG solve 9.20 to 9.00 ms)
+  for (int a0 = 0; a0 < TM; a0 += RB) {
 #pragma unroll 16
-  for (int a = 0; a < TM; ++a) {
-    const double v = __builtin_nontemporal_load(src + a * TM);
-    col += v * __shfl(bJ, a, TM);
-    prod[a][lane] = v * bI;
-  }
-  __syncthreads();
-  double row = 0.0;
+    for (int a = 0; a < RB; ++a) {
+      const double v = __builtin_nontemporal_load(src + (a0 + a) * TM);
+      col += v * __shfl(bJ, a0 + a, TM);
+      prod[a][lane] = v * bI;
+    }
+    __syncthreads();
+    if (lane >= a0 && lane < a0 + RB) {
 #pragma unroll 8
-  for (int c = 0; c < TM; ++c) row += prod[lane][c];
+      for (int c = 0; c < TM; ++c) row += prod[lane - a0][c];
+    }
+    __syncthreads();
+  }
   double* out = part + (int64_t)p * nb * nb * TM;
   out[((int64_t)J * nb + I) * TM + lane] = row;
   if (J > I) out[((int64_t)I * nb + J) * TM + lane] = col;
@@ -302,11 +308,16 @@ int dense_spd_inverse(hipStream_t s, int nbatch, int64_t np64, double* dense, in
   return AMG_OK;
 }
 
+// Half a tile through LDS at a time (16.6 KB per wavefront instead of 33 KB, so twice the
+// wavefronts per CU): 4096 rows 21.8 -> 19.7 us, 32 stacked problems of 4096 rows (2.2 GB of
+// tiles) 428 -> 391 us; a quarter (16 rows) is slower (30.6 and 565 us).
+constexpr int kSymvRows = 32;
+
 template <typename T>
 int launch_coarse_symv(hipStream_t s, int nbatch, int64_t nl, int64_t np, const double* ainv, const T* b, T* x,
                        double* part) {
   const int nb = (int)(np / TM), ntiles = nb * (nb + 1) / 2;
-  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(ntiles, nbatch), dim3(TM), 0, s, nb, ntiles, nl, ainv, b, part);
+  hipLaunchKernelGGL((k_symv_tiles<T, kSymvRows>), dim3(ntiles, nbatch), dim3(TM), 0, s, nb, ntiles, nl, ainv, b, part);
   hipLaunchKernelGGL(k_symv_sum<T>, dim3(nb, nbatch), dim3(256), 0, s, nb, nl, (const double*)part, x);
   return hipGetLastError() == hipSuccess ? AMG_OK : AMG_EHIP;
 }
