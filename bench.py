@@ -140,13 +140,14 @@ def vcycle_bytes(levels, w, kind, k, nbatch=1):
 
 def solve_bytes(levels, M0_64, w, kind, k, iters, flexible):
     """One PCG solve from x = 0: b checks and copies, then per iteration the CG product with the
-    direction update, the x / r update, one V-cycle (FP32: with the casts) and its dot products."""
+    direction update and the previous iteration's x += alpha p (not in the first), the r update,
+    one V-cycle (FP32: with the casts) and its dot products; the last x += alpha p after the loop."""
     n = levels[0][0]
     wz = w  # the CG kernels read the hierarchy's own output
     vc = vcycle_bytes(levels, w, kind, k) + (12 * n if w == 4 else 0)
     dots = (8 + wz) * n + (8 * n if flexible else 0)
-    per_it = (M0_64 + (24 + wz) * n) + (48 + (8 if flexible else 0)) * n + vc + dots
-    return 48 * n + iters * per_it
+    per_it = (M0_64 + (24 + wz + 16) * n) + (24 + (8 if flexible else 0)) * n + vc + dots
+    return 48 * n - 16 * n + iters * per_it + 24 * n
 
 
 def csr_model_step(nnz, n):

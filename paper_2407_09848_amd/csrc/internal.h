@@ -279,12 +279,16 @@ int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y);
 template <typename TZ>
 int launch_dot2(hipStream_t s, int64_t n, const double* a, const TZ* b, const double* c, const TZ* d,
                 double* partial, unsigned* nblocks);  // (a,b) and optionally (c,d)
-// p_new = z + beta p_old (beta from scal), q = A p_new, partials of (p_new, q)
+// p_new = z + beta p_old (beta from scal), q = A p_new, partials of (p_new, q); x (optional)
+// receives the previous iteration's x += alpha p_old (alpha from scal)
 template <typename TZ>
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const TZ* z, const double* pold,
-                      double* pnew, double* q, double* partial, unsigned* nblocks);
-int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
-                     double* r, double* rold, double* partial, unsigned* nblocks);
+                      double* pnew, double* q, double* partial, double* x, unsigned* nblocks);
+// r -= alpha q, partials of (r, r); rold (optional) receives the old r
+int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* q, double* r, double* rold,
+                     double* partial, unsigned* nblocks);
+// x += alpha p: the last iteration's update of x
+int launch_cg_x(hipStream_t s, int64_t n, const double* scal, const double* p, double* x);
 // pub (optional, RED_RR): receives (r, r) and the breakdown / NaN flags, for the host
 int launch_reduce(hipStream_t s, int mode, unsigned nblocks, const double* partial, double* scal, int* flag,
                   double* pub = nullptr);

@@ -813,6 +813,8 @@ __global__ __launch_bounds__(kBlock) void k_dot2(int64_t n, const double* __rest
 // q = A p_new, with (p_new, q) partials.  p_new of a neighbour is formed on the
 // fly from z and p_old (exactly the value stored for it), so p_new is written
 // to the other buffer of a pair.  z may be float (exactly converted, as in k_dot2).
+// x (optional): the previous iteration's x += alpha p_old (alpha still in the device scalars),
+// done here because the pass reads p_old anyway; the update kernel then leaves x alone.
 // PRE: p_new was formed beforehand by k_form_p (streaming levels): the product gathers one vector
 // instead of two (measured on a 27-point level of 32.8M rows: 1.36 ms + 0.13 ms for the separate
 // pass, against 1.77 ms with z and p_old both gathered; 7-point 256^3: 0.191 + 0.071 against
@@ -821,7 +823,7 @@ template <bool NT, typename TZ, bool PRE, bool W = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double> A, const double* __restrict__ scal,
                                                        const TZ* __restrict__ z, const double* __restrict__ pold,
                                                        double* pnew, double* __restrict__ q,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, double* __restrict__ x) {
   // with an FP32 hierarchy (float z) this product is the only reader of the FP64 matrix, once
   // per iteration: its values are streamed so that they do not displace the FP32 smoother's
   // matrix and vectors from the caches (128^3: FP32-hierarchy solve 6.63 to 6.36 ms)
@@ -854,8 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
     if constexpr (PRE) {
       pi = W ? pw : pnew[i];
     } else {
-      pi = z[i] + beta * pold[i];
+      const double po = pold[i];
+      pi = z[i] + beta * po;
       st<NT>(pnew + i, pi);
+      if (x) st<NT>(x + i, ld<NT>(x + i) + scal[S_ALPHA] * po);
     }
     st<NT>(q + i, acc);
     v = pi * acc;
@@ -864,29 +868,39 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_p(int64_t n, EllView<double
   if (threadIdx.x == 0) partial[logical_block()] = sum;
 }
 
-// p_new = z + beta p_old (beta from the device scalars), the expression of k_spmv_dot_p
+// p_new = z + beta p_old (beta from the device scalars), the expression of k_spmv_dot_p, and
+// (x given) the previous iteration's x += alpha p_old, as there
 template <bool NT, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_form_p(int64_t n, const double* __restrict__ scal,
                                                    const TZ* __restrict__ z, const double* __restrict__ pold,
-                                                   double* __restrict__ pnew) {
+                                                   double* __restrict__ pnew, double* __restrict__ x) {
   const int64_t i = row_index();
   if (i >= n) return;
-  const double beta = scal[S_BETA];
-  pnew[i] = (double)ld<NT>(z + i) + beta * ld<NT>(pold + i);
+  const double po = ld<NT>(pold + i);
+  pnew[i] = (double)ld<NT>(z + i) + scal[S_BETA] * po;
+  if (x) st<NT>(x + i, ld<NT>(x + i) + scal[S_ALPHA] * po);
 }
 
-// x += alpha p, r -= alpha q (alpha from the device scalars), partial (r, r);
-// rold (flexible CG) receives the previous r.
+// x += alpha p (alpha from the device scalars): the last iteration's update of x, which the
+// iterations before leave to the next direction pass
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_cg_x(int64_t n, const double* __restrict__ scal,
+                                                 const double* __restrict__ p, double* __restrict__ x) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  st<NT>(x + i, ld<NT>(x + i) + scal[S_ALPHA] * ld<NT>(p + i));
+}
+
+// r -= alpha q (alpha from the device scalars), partial (r, r); rold (flexible CG) receives the
+// previous r.  x is updated by the next direction pass (k_form_p, k_spmv_dot_p) or k_cg_x.
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ scal,
-                                                      const double* __restrict__ p, const double* __restrict__ q,
-                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ q, double* __restrict__ r,
                                                       double* __restrict__ rold, double* __restrict__ partial) {
   const int64_t i = row_index();
   const double alpha = scal[S_ALPHA];
   double v = 0.0;
   if (i < n) {
-    st<NT>(x + i, ld<NT>(x + i) + alpha * ld<NT>(p + i));
     const double ro = ld<NT>(r + i);
     if (rold) st<NT>(rold + i, ro);
     const double rn = ro - alpha * ld<NT>(q + i);
@@ -1335,36 +1349,45 @@ template int launch_dot2<float>(hipStream_t, int64_t, const double*, const float
 
 template <typename TZ>
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const TZ* z, const double* pold,
-                      double* pnew, double* q, double* partial, unsigned* nblocks) {
+                      double* pnew, double* q, double* partial, double* x, unsigned* nblocks) {
   const unsigned g = xcd_grid(A.n);
   if (streamed(g)) {
-    hipLaunchKernelGGL((k_form_p<true, TZ>), dim3(g), dim3(kBlock), 0, s, A.n, scal, z, pold, pnew);
+    hipLaunchKernelGGL((k_form_p<true, TZ>), dim3(g), dim3(kBlock), 0, s, A.n, scal, z, pold, pnew, x);
     if (wide(A))
       hipLaunchKernelGGL((k_spmv_dot_p<true, TZ, true, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z,
-                         pold, pnew, q, partial);
+                         pold, pnew, q, partial, nullptr);
     else
       hipLaunchKernelGGL((k_spmv_dot_p<true, TZ, true>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold,
-                         pnew, q, partial);
+                         pnew, q, partial, nullptr);
   } else {
     hipLaunchKernelGGL((k_spmv_dot_p<false, TZ, false>), dim3(g), dim3(kBlock), 0, s, A.n, view(A), scal, z, pold,
-                       pnew, q, partial);
+                       pnew, q, partial, x);
   }
   *nblocks = g;
   return LAUNCH_OK();
 }
 template int launch_spmv_dot_p<double>(hipStream_t, const Ell<double>&, const double*, const double*, const double*,
-                                       double*, double*, double*, unsigned*);
+                                       double*, double*, double*, double*, unsigned*);
 template int launch_spmv_dot_p<float>(hipStream_t, const Ell<double>&, const double*, const float*, const double*,
-                                      double*, double*, double*, unsigned*);
+                                      double*, double*, double*, double*, unsigned*);
 
-int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* p, const double* q, double* x,
-                     double* r, double* rold, double* partial, unsigned* nblocks) {
+int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* q, double* r, double* rold,
+                     double* partial, unsigned* nblocks) {
   const unsigned g = xcd_grid(n);
   if (streamed(g))
-    hipLaunchKernelGGL(k_cg_update<true>, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
+    hipLaunchKernelGGL(k_cg_update<true>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial);
   else
-    hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, p, q, x, r, rold, partial);
+    hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial);
   *nblocks = g;
+  return LAUNCH_OK();
+}
+
+int launch_cg_x(hipStream_t s, int64_t n, const double* scal, const double* p, double* x) {
+  const unsigned g = xcd_grid(n);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_cg_x<true>, dim3(g), dim3(kBlock), 0, s, n, scal, p, x);
+  else
+    hipLaunchKernelGGL(k_cg_x<false>, dim3(g), dim3(kBlock), 0, s, n, scal, p, x);
   return LAUNCH_OK();
 }
 

@@ -939,12 +939,14 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   double rel_prev = rel0, rate = 1.0;
   for (int it = 1; it <= maxit; ++it) {
     unsigned nb = 0;
+    // x += alpha p of the previous iteration rides on the pass that forms the new direction
+    double* xprev = it > 1 ? x : nullptr;
     if (z32)
-      AMGP_TRY(launch_spmv_dot_p<float>(s, A, h->scal, z32, pold, p, q, h->partial, &nb));
+      AMGP_TRY(launch_spmv_dot_p<float>(s, A, h->scal, z32, pold, p, q, h->partial, xprev, &nb));
     else
-      AMGP_TRY(launch_spmv_dot_p<double>(s, A, h->scal, z, pold, p, q, h->partial, &nb));
+      AMGP_TRY(launch_spmv_dot_p<double>(s, A, h->scal, z, pold, p, q, h->partial, xprev, &nb));
     AMGP_TRY(launch_reduce(s, RED_ALPHA, nb, h->partial, h->scal, h->dflag));
-    AMGP_TRY(launch_cg_update(s, n, h->scal, p, q, x, r, rold, h->partial, &nb));
+    AMGP_TRY(launch_cg_update(s, n, h->scal, q, r, rold, h->partial, &nb));
     AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag, h->dpub));
     AMGP_HIP(hipEventRecord(h->ev, s));
     const bool ahead = it < maxit && rel_prev * rate > 2.0 * rtol;
@@ -957,6 +959,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
     *relres = rel;
     if (hist) hist[it] = rel;
     if (breakdown || nan || rel <= rtol || it == maxit) {
+      AMGP_TRY(launch_cg_x(s, n, h->scal, p, x));  // this iteration's x += alpha p (alpha = 0 on breakdown)
       AMGP_HIP(hipStreamSynchronize(s));
       if (breakdown) return AMG_EBREAKDOWN;
       if (nan) return AMG_ENAN;
