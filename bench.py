@@ -138,15 +138,19 @@ def vcycle_bytes(levels, w, kind, k, nbatch=1):
     return tot
 
 
-def solve_bytes(levels, M0_64, w, kind, k, iters, flexible):
+def solve_bytes(levels, M0_64, w, kind, k, iters, flexible, u_path=False):
     """One PCG solve from x = 0: b checks and copies, then per iteration the CG product with the
     direction update and the previous iteration's x += alpha p (not in the first), the r update,
-    one V-cycle (FP32: with the casts) and its dot products; the last x += alpha p after the loop."""
+    one V-cycle (FP32: with the casts) and its dot products; the last x += alpha p after the loop.
+    u_path: the r update also writes u = M^-1 r (reading M^-1), which the V-cycle's merged first
+    two steps read in place of the gathered M^-1 and r (large 27-point FP64 fine levels)."""
     n = levels[0][0]
     wz = w  # the CG kernels read the hierarchy's own output
     vc = vcycle_bytes(levels, w, kind, k) + (12 * n if w == 4 else 0)
     dots = (8 + wz) * n + (8 * n if flexible else 0)
     per_it = (M0_64 + (24 + wz + 16) * n) + (24 + (8 if flexible else 0)) * n + vc + dots
+    if u_path:
+        per_it += 24 * n
     return 48 * n - 16 * n + iters * per_it + 24 * n
 
 
@@ -545,7 +549,12 @@ def main():
     L = amg.amg_num_levels(h)
     lv64 = level_table(amg, h, 8)
     M0 = lv64[0][1]
-    value = solve_bytes(lv64, M0, 8, args.kind, args.degree, it, False) / (ms * 1e-3) / 1e9
+    padded, lanes, aligned = amg.amg_level_layout(h, 0)
+    streams = ((n0 + 255) // 256 + 7) // 8 * 8 > STREAM_MIN_BLOCKS
+    # wide slices (at least 24 stored steps per row on average) take the wide-batch variant
+    wide = streams and aligned and lanes == 1 and padded >= WIDE_MIN_STEPS * n0
+    u_path = wide and args.kind != 0 and args.degree >= 2
+    value = solve_bytes(lv64, M0, 8, args.kind, args.degree, it, False, u_path) / (ms * 1e-3) / 1e9
 
     progress(f"headline solves: {ms:.1f} ms, {it} iterations")
     # ---- the fine level's fused step ----
@@ -553,13 +562,9 @@ def main():
     t_step = fused_step_time(amg, h, args.kind, bd, xs, stream)
     step_bytes = fused_bytes(n0, M0, 8, True, True)
     achieved = step_bytes / (t_step * 1e-3) / 1e9
-    padded, lanes, aligned = amg.amg_level_layout(h, 0)
     csr_bytes = csr_model_step(nnz0, n0)
     progress(f"fused step: {t_step * 1e3:.1f} us")
     ceil = ceiling(amg, stream)
-    streams = ((n0 + 255) // 256 + 7) // 8 * 8 > STREAM_MIN_BLOCKS
-    # wide slices (at least 24 stored steps per row on average) take the wide-batch variant
-    wide = streams and aligned and lanes == 1 and padded >= WIDE_MIN_STEPS * n0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
                 "kernel": f"k_fused<double,0,true,{str(streams).lower()},1,{str(wide).lower()}> (fine level, "

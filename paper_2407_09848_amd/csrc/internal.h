@@ -201,7 +201,7 @@ struct Handle {
   hipEvent_t ev = nullptr;    // end of a CG update (the host waits on it)
   int* dflag = nullptr;       // device error flags
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_p2 = nullptr, *cg_q = nullptr, *cg_rold = nullptr;
-  double *tmp64 = nullptr;    // level-0 scratch (n0)
+  double* cg_u = nullptr;     // M^{-1} r of level 0, for the V-cycle's first kernel (n0)
   double& beta_at(int l, int k, int j) {
     return beta[((size_t)l * (AMG_MAX_DEGREE + 1) + k) * AMG_MAX_DEGREE + j];
   }
@@ -241,7 +241,9 @@ int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* m
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
                        T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v = Wt(),
-                       Wt w2v = Wt());
+                       Wt w2v = Wt(), const T* u = nullptr);
+// u = M^{-1} b, given to launch_first2_zero, is read on these levels (and ignored on the others)
+bool first2_takes_u(const Ell<double>& A);
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c, Prol<T> pr = Prol<T>());  // pr: A.group must be 1
@@ -284,9 +286,9 @@ int launch_dot2(hipStream_t s, int64_t n, const double* a, const TZ* b, const do
 template <typename TZ>
 int launch_spmv_dot_p(hipStream_t s, const Ell<double>& A, const double* scal, const TZ* z, const double* pold,
                       double* pnew, double* q, double* partial, double* x, unsigned* nblocks);
-// r -= alpha q, partials of (r, r); rold (optional) receives the old r
+// r -= alpha q, partials of (r, r); rold (optional) receives the old r, u (optional) M^{-1} r
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* q, double* r, double* rold,
-                     double* partial, unsigned* nblocks);
+                     double* partial, unsigned* nblocks, const double* minv = nullptr, double* u = nullptr);
 // x += alpha p: the last iteration's update of x
 int launch_cg_x(hipStream_t s, int64_t n, const double* scal, const double* p, double* x);
 // pub (optional, RED_RR): receives (r, r) and the breakdown / NaN flags, for the host

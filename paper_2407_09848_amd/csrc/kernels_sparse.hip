@@ -465,11 +465,13 @@ __global__ __launch_bounds__(kBlock) void k_first_zero(int64_t n, const T* __res
 // vectors disappears.
 // MODE 0: g1 = c1 M^{-1} b, r1 = b - A g1, g2 = alpha g1 + c M^{-1} r1, x = w1 g1 + w2 g2.
 // MODE 1: r0 = M^{-1} b, d0 = r0 / theta, r1 = r0 - M^{-1} A d0, d1 = alpha d0 + c r1, x = d0 + d1.
-template <typename T, int MODE, bool STORE, bool NT, int G, bool W = false>
+// U: u = M^{-1} b (the same products) was written beforehand by the kernel that produced b (the
+// CG's residual update), so the neighbours' step-1 directions gather one vector instead of two.
+template <typename T, int MODE, bool STORE, bool NT, int G, bool W = false, bool U = false>
 __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                                         const T* __restrict__ b, T* __restrict__ gnew,
                                                         T* __restrict__ r, T* __restrict__ x, T c1, T alpha, T c,
-                                                        T w1, T w2, Wt w1v, Wt w2v) {
+                                                        T w1, T w2, Wt w1v, Wt w2v, const T* __restrict__ u) {
   const int64_t i = row_of_thread<G>();
   if (exit_rows<G>(i, n)) return;
   constexpr int R = kSlice / G;
@@ -483,21 +485,23 @@ __global__ __launch_bounds__(kBlock) void k_first2_zero(int64_t n, EllView<T> A,
     bi = b[i];
   }
   T ag = T(0);
+  auto g1of = [&](int j) {
+    const T mb = U ? u[j] : minv[j] * b[j];
+    return (MODE == 0) ? c1 * mb : mb / c1;
+  };
   if (G == 1 && A.doff) {
     const int32_t* off = A.doff + (beg >> 6);
-    auto g1 = [&](int j) { return (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1; };
     if constexpr (std::is_same_v<T, float>) {
-      ag = aligned_sum_f32<NT>(A.val, beg, end, lane, off, (int)i, A.last, g1);
+      ag = aligned_sum_f32<NT>(A.val, beg, end, lane, off, (int)i, A.last, g1of);
     } else {
-      ag = aligned_sum_f64<NT, decltype(g1), true, W ? kWideBatch : kAlignedBatch>(A.val, beg, end, lane, off, (int)i,
-                                                                                    A.last, g1);
+      ag = aligned_sum_f64<NT, decltype(g1of), true, W ? kWideBatch : kAlignedBatch>(A.val, beg, end, lane, off, (int)i,
+                                                                                    A.last, g1of);
     }
   } else {
 #pragma unroll 4
     for (int p = beg + lane; p < end; p += kSlice) {
       const int j = ld<NT>(A.col + p);
-      const T g1j = (MODE == 0) ? c1 * (minv[j] * b[j]) : (minv[j] * b[j]) / c1;
-      ag += ld<NT>(A.val + p) * g1j;
+      ag += ld<NT>(A.val + p) * g1of(j);
     }
   }
   if constexpr (G > 1) {
@@ -893,10 +897,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_x(int64_t n, const double* __rest
 
 // r -= alpha q (alpha from the device scalars), partial (r, r); rold (flexible CG) receives the
 // previous r.  x is updated by the next direction pass (k_form_p, k_spmv_dot_p) or k_cg_x.
+// u (optional) receives M^{-1} r for the preconditioner's first kernel (k_first2_zero, U).
 template <bool NT>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* __restrict__ scal,
                                                       const double* __restrict__ q, double* __restrict__ r,
-                                                      double* __restrict__ rold, double* __restrict__ partial) {
+                                                      double* __restrict__ rold, double* __restrict__ partial,
+                                                      const double* __restrict__ minv, double* __restrict__ u) {
   const int64_t i = row_index();
   const double alpha = scal[S_ALPHA];
   double v = 0.0;
@@ -905,6 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, const double* _
     if (rold) st<NT>(rold + i, ro);
     const double rn = ro - alpha * ld<NT>(q + i);
     r[i] = rn;
+    if (u) st<NT>(u + i, minv[i] * rn);
     v = rn * rn;
   }
   const double s = block_sum(v);
@@ -1026,6 +1033,9 @@ inline bool wide(const Ell<double>& A) {
   return A.doff && A.group == 1 && A.padded >= (int64_t)kWideMinSteps * A.n;
 }
 
+// The levels whose merged first two steps can read u = M^{-1} b instead of gathering M^{-1} and b
+bool first2_takes_u(const Ell<double>& A) { return streamed(xcd_grid(A.n)) && wide(A); }
+
 // Runs f(std::integral_constant<int, G>) for the matrix's lanes per row G.
 template <typename F>
 int with_group(int group, F&& f) {
@@ -1094,27 +1104,29 @@ int launch_first_zero(hipStream_t s, int mode, bool store, int64_t n, const T* m
   return LAUNCH_OK();
 }
 
-template <typename T, bool NT, int G, bool W = false>
+template <typename T, bool NT, int G, bool W = false, bool U = false>
 void go_first2_zero(dim3 gr, hipStream_t s, int mode, bool store, EllView<T> A, int64_t n, const T* minv,
-                    const T* b, T* gnew, T* r, T* x, T a1, T a2, T a3, T a4, T a5, Wt w1v, Wt w2v) {
+                    const T* b, T* gnew, T* r, T* x, T a1, T a2, T a3, T a4, T a5, Wt w1v, Wt w2v,
+                    const T* u = nullptr) {
   dim3 bl(kBlock);
   if (mode == 0 && store)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
-                       a4, a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, true, NT, G, W, U>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2,
+                       a3, a4, a5, w1v, w2v, u);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
-                       a4, a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 0, false, NT, G, W, U>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2,
+                       a3, a4, a5, w1v, w2v, u);
   else if (store)
-    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
-                       a4, a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, true, NT, G, W, U>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2,
+                       a3, a4, a5, w1v, w2v, u);
   else
-    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT, G, W>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2, a3,
-                       a4, a5, w1v, w2v);
+    hipLaunchKernelGGL((k_first2_zero<T, 1, false, NT, G, W, U>), gr, bl, 0, s, n, A, minv, b, gnew, r, x, a1, a2,
+                       a3, a4, a5, w1v, w2v, u);
 }
 
 template <typename T>
 int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* minv, const T* b, T* gnew,
-                       T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v, Wt w2v) {
+                       T* r, T* x, double c1, double alpha, double c, double w1, double w2, Wt w1v, Wt w2v,
+                       const T* u) {
   return with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
     const dim3 gr(xcd_grid(A.n * G));
@@ -1122,8 +1134,12 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
       if (streamed(gr.x)) {
         if constexpr (std::is_same_v<T, double>) {
           if (wide(A)) {
-            go_first2_zero<T, true, 1, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha,
-                                             (T)c, (T)w1, (T)w2, w1v, w2v);
+            if (u)
+              go_first2_zero<T, true, 1, true, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1,
+                                                     (T)alpha, (T)c, (T)w1, (T)w2, w1v, w2v, u);
+            else
+              go_first2_zero<T, true, 1, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1,
+                                               (T)alpha, (T)c, (T)w1, (T)w2, w1v, w2v);
             return;
           }
         }
@@ -1372,12 +1388,12 @@ template int launch_spmv_dot_p<float>(hipStream_t, const Ell<double>&, const dou
                                       double*, double*, double*, double*, unsigned*);
 
 int launch_cg_update(hipStream_t s, int64_t n, const double* scal, const double* q, double* r, double* rold,
-                     double* partial, unsigned* nblocks) {
+                     double* partial, unsigned* nblocks, const double* minv, double* u) {
   const unsigned g = xcd_grid(n);
   if (streamed(g))
-    hipLaunchKernelGGL(k_cg_update<true>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial);
+    hipLaunchKernelGGL(k_cg_update<true>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial, minv, u);
   else
-    hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial);
+    hipLaunchKernelGGL(k_cg_update<false>, dim3(g), dim3(kBlock), 0, s, n, scal, q, r, rold, partial, minv, u);
   *nblocks = g;
   return LAUNCH_OK();
 }
@@ -1417,7 +1433,7 @@ int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag) {
   template int launch_first_zero<T>(hipStream_t, int, bool, int64_t, const T*, const T*, T*, T*, T*, double,   \
                                     double, Wt);                                                              \
   template int launch_first2_zero<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, T*, T*,    \
-                                     double, double, double, double, double, Wt, Wt);                         \
+                                     double, double, double, double, double, Wt, Wt, const T*);               \
   template int launch_first_res<T>(hipStream_t, int, const Ell<T>&, const T*, const T*, const T*, T*, T*,      \
                                    double, Prol<T>);                                                          \
   template int launch_fused<T>(hipStream_t, int, bool, const Ell<T>&, const T*, const T*, T*, const T*, T*, T*,  \

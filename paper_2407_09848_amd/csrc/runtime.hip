@@ -105,7 +105,7 @@ void release(Handle* h) {
   hipFree(h->cg_p2);
   hipFree(h->cg_q);
   hipFree(h->cg_rold);
-  hipFree(h->tmp64);
+  hipFree(h->cg_u);
   free_adj(h->adj64);
   free_adj(h->adj32);
   hipFree(h->tr_buf);
@@ -139,9 +139,11 @@ inline Wt step_weight(const Handle* h, int l, int kind, int k, int j) {
 // r0_copy (optional, x_in != 0 only): receives r^(0) = b - A x_in, the input of the recurrence.
 // pr (optional, x_in != 0, Chebyshev kinds, one row per lane): the smoother runs on
 // x_in + P x_c, the box prolongation being applied inside its first two kernels.
+// u (optional, x = 0): M^{-1} b, written by the kernel that produced b, for the merged first
+// two steps.
 template <typename T>
 int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStream_t s, T* r0_copy = nullptr,
-           Prol<T> pr = Prol<T>()) {
+           Prol<T> pr = Prol<T>(), const T* u = nullptr) {
   Level& L = h->lv[l];
   const Ell<T>& A = Prec<T>::A(L);
   Vecs<T>& v = Prec<T>::v(L);
@@ -180,7 +182,7 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
       // steps 1 and 2 in one pass
       const double alpha2 = (2.0 * 2 - 3.0) / (2.0 * 2 + 1.0), c2 = (8.0 * 2 - 4.0) / (2.0 * 2 + 1.0);
       AMGP_TRY(launch_first2_zero<T>(s, 0, k > 2, A, minv, b, g[1 - cur], v.r, x, c1, alpha2, c2, w(1), w(2),
-                                     step_weight(h, l, kind, k, 1), step_weight(h, l, kind, k, 2)));
+                                     step_weight(h, l, kind, k, 1), step_weight(h, l, kind, k, 2), u));
       rsrc = v.r;
       cur = 1 - cur;
       j0 = 3;
@@ -222,7 +224,7 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
     // steps 0 and 1 of Algorithm 1 in one pass
     const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
     AMGP_TRY(launch_first2_zero<T>(s, 1, k > 2, A, minv, b, g[1 - cur], v.r, x, theta, rho * rho_prev,
-                                   2.0 * rho / delta, 1.0, 1.0));
+                                   2.0 * rho / delta, 1.0, 1.0, Wt(), Wt(), u));
     rho_prev = rho;
     cur = 1 - cur;
     j0 = 2;
@@ -287,13 +289,13 @@ int prolong_set(Handle* h, int l, const T* yc, T* y, hipStream_t s) {
 
 constexpr int64_t kFusedTransferMaxRows = 1 << 20;
 
-// V-cycle of eq. (amg) from level l: x = B_l b.
+// V-cycle of eq. (amg) from level l: x = B_l b.  u (optional): M^{-1} b for the pre-smoothing.
 template <typename T>
-int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s) {
+int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s, const T* u = nullptr) {
   if (l == h->nlevels - 1) return coarse<T>(h, b, x, s);
   Level& L = h->lv[l];
   Vecs<T>& vc = Prec<T>::v(h->lv[l + 1]);
-  AMGP_TRY(smooth<T>(h, l, kind, k, b, x, true, s));
+  AMGP_TRY(smooth<T>(h, l, kind, k, b, x, true, s, nullptr, Prol<T>(), u));
   AMGP_TRY(restrict_res<T>(h, l, b, x, Prec<T>::v(L).r, vc.b, s));
   AMGP_TRY(vcycle<T>(h, l + 1, kind, k, vc.b, vc.x, s));
   // small box levels with one row per lane: the prolongation rides on the post-smoothing's
@@ -309,7 +311,8 @@ int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s) {
 
 // keep32 (FP32 hierarchy): leave the result in the level-0 float vector v32.x instead of
 // converting it into z (the CG kernels read it there).
-int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s, bool keep32 = false) {
+int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s, bool keep32 = false,
+               const double* u = nullptr) {
   if (h->precision == AMG_FP32) {
     Vecs<float>& v = h->lv[0].v32;
     AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
@@ -317,7 +320,7 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
     if (keep32) return AMG_OK;
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
-  return vcycle<double>(h, 0, kind, k, r, z, s);
+  return vcycle<double>(h, 0, kind, k, r, z, s, u);
 }
 
 // The V-cycle as one HIP graph: captured on the handle's own stream the first
@@ -836,7 +839,7 @@ int setup(Handle* h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32
   AMGP_TRY(dalloc(&h->cg_p2, n0));
   AMGP_TRY(dalloc(&h->cg_q, n0));
   AMGP_TRY(dalloc(&h->cg_rold, n0));
-  AMGP_TRY(dalloc(&h->tmp64, n0));
+  AMGP_TRY(dalloc(&h->cg_u, n0));
   // default coefficients
   h->beta.assign((size_t)h->nlevels * (AMG_MAX_DEGREE + 1) * AMG_MAX_DEGREE, 0.0);
   for (int l = 0; l < h->nlevels; ++l)
@@ -880,12 +883,13 @@ int fetch_scalars(Handle* h, hipStream_t s) {
 // captured together as one graph.  B is the V-cycle, or with poly the level-0 smoother
 // alone from z = 0 (the polynomial preconditioning of the remark after Fig. boundcomparison).
 int precond_dot(Handle* h, int kind, int k, bool poly, int mode, const double* r, double* z, const double* rold,
-                hipStream_t s) {
+                hipStream_t s, const double* u = nullptr) {
   const int64_t n = h->lv[0].n;
-  const GraphEntry key{kind, k, mode, poly, r, z, rold, nullptr};
+  const GraphEntry key{kind, k, mode, poly, r, z, rold, nullptr};  // u is fixed by (h, kind, k, mode)
   const float* z32 = cg_z32(h, poly);
   return run_graph(h, key, s, [&](hipStream_t cs) {
-    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs) : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr));
+    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs, nullptr, Prol<double>(), u)
+                  : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr, u));
     if (z32) return sum_dot<float>(h, cs, mode, r, z32, mode == RED_BETA_FLEX ? rold : nullptr,
                                    mode == RED_BETA_FLEX ? z32 : nullptr, n);
     if (mode == RED_BETA_FLEX) return sum_dot<double>(h, cs, mode, r, z, rold, z, n);
@@ -935,6 +939,10 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
   AMGP_TRY(precond_dot(h, kind, k, poly_only, RED_RZ0, r, z, nullptr, s));  // also beta = 0: p_1 = z_0
   double* pold = h->cg_p2;
   AMGP_TRY(launch_fill<double>(s, n, 0.0, pold));
+  // on large 27-point FP64 levels the residual update also writes u = M^{-1} r, so that the
+  // preconditioner's merged first two steps gather u alone instead of M^{-1} and r
+  double* u = h->precision == AMG_FP64 && kind != AMG_L1JAC && k >= 2 && first2_takes_u(A) ? h->cg_u : nullptr;
+  const double* minv0 = h->lv[0].v64.minv;
   const int next_mode = flex ? RED_BETA_FLEX : RED_BETA;
   double rel_prev = rel0, rate = 1.0;
   for (int it = 1; it <= maxit; ++it) {
@@ -946,11 +954,11 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
     else
       AMGP_TRY(launch_spmv_dot_p<double>(s, A, h->scal, z, pold, p, q, h->partial, xprev, &nb));
     AMGP_TRY(launch_reduce(s, RED_ALPHA, nb, h->partial, h->scal, h->dflag));
-    AMGP_TRY(launch_cg_update(s, n, h->scal, q, r, rold, h->partial, &nb));
+    AMGP_TRY(launch_cg_update(s, n, h->scal, q, r, rold, h->partial, &nb, minv0, u));
     AMGP_TRY(launch_reduce(s, RED_RR, nb, h->partial, h->scal, h->dflag, h->dpub));
     AMGP_HIP(hipEventRecord(h->ev, s));
     const bool ahead = it < maxit && rel_prev * rate > 2.0 * rtol;
-    if (ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s));
+    if (ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s, u));
     AMGP_HIP(hipEventSynchronize(h->ev));
     *iters = it;
     const double rr = h->hpub[0];
@@ -965,7 +973,7 @@ int pcg(Handle* h, int kind, int k, const double* b, double* x, bool xz, double 
       if (nan) return AMG_ENAN;
       return rel <= rtol ? AMG_OK : AMG_NOT_CONVERGED;
     }
-    if (!ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s));
+    if (!ahead) AMGP_TRY(precond_dot(h, kind, k, poly_only, next_mode, r, z, rold, s, u));
     rate = rel / rel_prev;
     rel_prev = rel;
     std::swap(p, pold);  // the next iteration forms p = z + beta pold inside its SpMV

@@ -460,6 +460,35 @@ def test_pcg_iterations_full_size_c2(amg):
             assert np.linalg.norm(b - A.to_scipy() @ xr) <= 1.05e-8 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("flexible", [False, True])
+def test_pcg_iterate_at_the_iteration_limit(amg, flexible):
+    """Solves stopped by their iteration limit (1, 2, 3 and 7 iterations) return the oracle's CG
+    iterate after as many iterations, with the V-cycle and with the smoother alone as the
+    preconditioner: inside the loop x trails by one iteration (its update rides on the next
+    direction pass), so the exit must add the last iteration's alpha p."""
+    torch = torch_cuda()
+    g = W.gaussian_random_field((30, 36, 40), 4.0, 91)
+    A = W.fv_diffusion(np.exp(g))
+    b = W.rhs_uniform(A.n, 92)
+    As = A.to_scipy()
+    H = OA.build_hierarchy(As, A.grid)
+    beta, _ = oracle_params(2, 4)
+    Minv = S.l1_diagonal(As)
+    preconds = {"pcg_solve": lambda r: OA.vcycle(H, r, 2, 4, beta),
+                "pcg_solve_smoother": lambda r: S.smooth(As, Minv, r, None, 2, 4, beta, None)}
+    with hierarchy(A) as h:
+        assert amg.amg_num_levels(h) == len(H.levels) > 1
+        for name, precond in preconds.items():
+            for maxit in (1, 2, 3, 7):
+                x = nan_vec(A.n)
+                rc, it, rel, _ = getattr(amg, name)(h, 2, 4, dev(b), x, True, 1e-14, maxit, flexible)
+                torch.cuda.synchronize()
+                ro = OA.pcg(As, b, precond, 1e-14, maxit, flexible)
+                assert rc == amg.AMG_NOT_CONVERGED and it == maxit == ro.iters, (name, maxit)
+                assert rel == pytest.approx(ro.relres, rel=1e-9), (name, maxit)
+                assert relerr(host(x), ro.x) <= 1e-10, (name, maxit, flexible)
+
+
 def test_pcg_deterministic(amg):
     torch = torch_cuda()
     A, b, _ = W.config_problem(2, size=48)

@@ -11,7 +11,8 @@ the element-wise and norm-wise bound of `relerr`):
   x != 0, and V-cycles;
 * 7-point 256^3 (16,777,216 rows, 65536 blocks: whole rounds only), the
   optimal kinds at degrees 1..6, the other two at 1, 4 and 6, and one V-cycle;
-* 27-point Q1 164^3 (4,410,944 rows, 17232 blocks: a tail of 848 blocks);
+* 27-point Q1 164^3 (4,410,944 rows, 17232 blocks: a tail of 848 blocks), and
+  CG preconditioned by its smoother (the residual update feeding M^-1 r to it);
 * the differentiable V-cycle and the training loss on 20 stacked 64^3
   diffusion problems (5,242,880 rows, 20480 blocks) at degree 6, against the
   oracle per problem and the complex-step derivative on sampled weights.
@@ -140,19 +141,48 @@ def test_streaming_vcycle_256(p256):
     assert e <= TOL
 
 
-def test_streaming_27pt_tail_blocks():
-    torch = torch_cuda()
-    import paper_2407_09848_amd as amg
+@pytest.fixture(scope="module")
+def p27():
+    torch_cuda()
     A = W.q1_27pt(164)
     assert _blocks(A.n) > STREAM_MIN_BLOCKS and ((_blocks(A.n) + 7) // 8 * 8) % XCD_ROUND == 848
-    pr = _Problem(A, 303)
-    with hierarchy(A) as h:
+    return _Problem(A, 303)
+
+
+def test_streaming_27pt_tail_blocks(p27):
+    torch_cuda()
+    import paper_2407_09848_amd as amg
+    pr = p27
+    with hierarchy(pr.A) as h:
         padded, lanes, aligned = amg.amg_level_layout(h, 0)
         assert aligned and lanes == 1
         errs = [_check_smoother(amg, h, pr, kind, 4, True) for kind in (2, 3)]
         errs.append(_check_smoother(amg, h, pr, 2, 3, False))
         errs.append(_check_smoother(amg, h, pr, 0, 2, True))
     _log(f"27-point 164^3: max error {max(errs):.2e}")
+
+
+def test_streaming_27pt_pcg_smoother_iterates(p27):
+    """CG preconditioned by the fine-level smoother alone on the 27-point level: from the second
+    iteration on, its residual update also writes u = M^-1 r, which the smoother's merged first
+    two steps read in place of the gathered M^-1 and r.  The iterate after three iterations
+    matches the oracle's CG iterate (kinds 1-3, degree 4)."""
+    torch = torch_cuda()
+    import paper_2407_09848_amd as amg
+    pr = p27
+    errs = []
+    with hierarchy(pr.A) as h:
+        for kind in (1, 2, 3):
+            beta, a = oracle_params(kind, 4)
+            x = nan_vec(pr.A.n)
+            rc, it, rel, _ = amg.pcg_solve_smoother(h, kind, 4, dev(pr.b), x, True, 1e-14, 3)
+            torch.cuda.synchronize()
+            ro = OA.pcg(pr.As, pr.b, lambda r: S.smooth(pr.As, pr.Minv, r, None, kind, 4, beta, a), 1e-14, 3)
+            assert rc == amg.AMG_NOT_CONVERGED and it == 3 == ro.iters, kind
+            assert rel == pytest.approx(ro.relres, rel=1e-9), kind
+            errs.append(relerr(host(x), ro.x))
+            assert errs[-1] <= 1e-10, (kind, errs[-1])
+    _log(f"27-point 164^3 smoother-preconditioned CG: max error {max(errs):.2e}")
 
 
 # ---------------------------------------------------------------------------
