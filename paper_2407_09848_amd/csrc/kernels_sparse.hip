@@ -375,15 +375,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, EllView<T> A, co
 // x itself, or a k_fused_keep_x step, which leaves x alone: the next step adds
 // both directions, which it reads anyway, in the same order).
 // STORE = false on the last step of an application: only x is needed.
+// Returns the x it stores (0 on rows that store none).
 // ---------------------------------------------------------------------------
 // W: wide slices (one row per lane): the row's vectors are requested before the product, whose
 // steps go in batches of kWideBatch.
 template <typename T, int MODE, bool STORE, bool NT, int G, bool XUPD, bool W>
-__device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __restrict__ minv,
+__device__ __forceinline__ T fused_step(int64_t n, EllView<T> A, const T* __restrict__ minv,
                                           const T* __restrict__ gold, T* __restrict__ gnew, const T* rin, T* rout,
                                           T* __restrict__ x, T alpha, T c, T w, T wprev, Wt wv, Wt wpv, Prol<T> pr) {
   const int64_t i = row_of_thread<G>();
-  if (exit_rows<G>(i, n)) return;
+  if (exit_rows<G>(i, n)) return T(0);
   T mi, go, ri, xi = T(0);
   if constexpr (W) {
     mi = ld_minv<NT, W>(minv + i);
@@ -392,7 +393,7 @@ __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __r
     if constexpr (XUPD) xi = ld<NT>(x + i);
   }
   const T ag = ell_dot<NT, G, W ? kWideBatch : kAlignedBatch>(A, i, gold);
-  if (!row_owner<G>(i, n)) return;
+  if (!row_owner<G>(i, n)) return T(0);
   if constexpr (!W) {
     mi = ld_minv<NT, W>(minv + i);
     go = gold[i];
@@ -400,17 +401,20 @@ __device__ __forceinline__ void fused_step(int64_t n, EllView<T> A, const T* __r
   }
   const T r = (MODE == 0) ? ri - ag : ri - mi * ag;
   const T g = (MODE == 0) ? alpha * go + c * (mi * r) : alpha * go + c * r;
+  T xn = T(0);
   if constexpr (XUPD) {
     w = wsel(wv, w, i);
     wprev = wsel(wpv, wprev, i);
     if constexpr (!W) xi = ld<NT>(x + i);
     if (pr.agg) xi = xi + pr.xc[pr.agg[i]];
-    st<NT>(x + i, xi + wprev * go + w * g);
+    xn = xi + wprev * go + w * g;
+    st<NT>(x + i, xn);
   }
   if (STORE) {
     st<NT>(rout + i, r);
     gnew[i] = g;
   }
+  return xn;
 }
 
 template <typename T, int MODE, bool STORE, bool NT, int G, bool W = false>
@@ -432,6 +436,34 @@ __global__ __launch_bounds__(kBlock) void k_fused_keep_x(int64_t n, EllView<T> A
 }
 
 // END fused-step
+
+// The last step of an application with the CG's dot products of its result fused in: block
+// partials of (dr, x) and, with drold, of (drold, x), over the x this step stores.  The products,
+// the block order and the sums are those of k_dot2 on the same grid, so the partials are the same
+// numbers.
+template <int MODE, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_fused_dot(int64_t n, EllView<double> A, const double* __restrict__ minv,
+                                                      const double* __restrict__ gold, const double* rin,
+                                                      double* __restrict__ x, double alpha, double c, double w,
+                                                      double wprev, Wt wv, Wt wpv, Prol<double> pr,
+                                                      const double* __restrict__ dr, const double* __restrict__ drold,
+                                                      double* __restrict__ partial) {
+  const double xn = fused_step<double, MODE, false, NT, 1, true, W>(n, A, minv, gold, nullptr, rin, nullptr, x, alpha,
+                                                                     c, w, wprev, wv, wpv, pr);
+  const int64_t i = row_index();
+  double v = 0.0, u = 0.0;
+  if (i < n) {
+    v = ld<NT>(dr + i) * xn;
+    if (drold) u = ld<NT>(drold + i) * xn;
+  }
+  const double sv = block_sum(v);
+  __syncthreads();
+  const double su = drold ? block_sum(u) : 0.0;
+  if (threadIdx.x == 0) {
+    partial[logical_block()] = sv;
+    partial[gridDim.x + logical_block()] = su;
+  }
+}
 
 // First step from x = 0 (r^(0) = b, no SpMV).
 // MODE 0: g = c M^{-1} b, x = w g.   MODE 1: r = M^{-1} b, g = r / c (c = theta), x = g.
@@ -1252,6 +1284,32 @@ int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* 
     go_fused<T, false, G>(gr, s, mode, store, view(A), A.n, minv, gold, gnew, rin, rout, x, (T)alpha, (T)c, (T)w,
                           (T)wprev, wv, wpv, pr);
   });
+}
+
+int launch_fused_dot(hipStream_t s, int mode, const Ell<double>& A, const double* minv, const double* gold,
+                     const double* rin, double* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv,
+                     Prol<double> pr, const double* dr, const double* drold, double* partial, unsigned* nblocks) {
+  if (A.group != 1) return AMG_EINVAL;
+  const dim3 gr(xcd_grid(A.n)), bl(kBlock);
+  auto go = [&](auto nt, auto wd) {
+    constexpr bool NT = decltype(nt)::value, W = decltype(wd)::value;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_fused_dot<0, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, alpha, c, w, wprev,
+                         wv, wpv, pr, dr, drold, partial);
+    else
+      hipLaunchKernelGGL((k_fused_dot<1, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, alpha, c, w, wprev,
+                         wv, wpv, pr, dr, drold, partial);
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (!streamed(gr.x))
+    go(F_(), F_());
+  else if (wide(A))
+    go(T_(), T_());
+  else
+    go(T_(), F_());
+  *nblocks = gr.x;
+  return LAUNCH_OK();
 }
 
 template <typename T>

@@ -137,13 +137,24 @@ inline Wt step_weight(const Handle* h, int l, int kind, int k, int j) {
 }
 
 // r0_copy (optional, x_in != 0 only): receives r^(0) = b - A x_in, the input of the recurrence.
+// The CG's dot products of a preconditioner result with r (and, flexible, r_old), taken by the
+// preconditioner's last kernel when that kernel is a recurrence step (done is then set).
+struct DotOut {
+  const double* r = nullptr;
+  const double* rold = nullptr;
+  double* partial = nullptr;
+  unsigned nb = 0;
+  bool done = false;
+};
+
 // pr (optional, x_in != 0, Chebyshev kinds, one row per lane): the smoother runs on
 // x_in + P x_c, the box prolongation being applied inside its first two kernels.
 // u (optional, x = 0): M^{-1} b, written by the kernel that produced b, for the merged first
-// two steps.
+// two steps.  dot (optional, FP64): the dot products of the result, see DotOut.
 template <typename T>
 int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStream_t s, T* r0_copy = nullptr,
-           Prol<T> pr = Prol<T>(), const T* u = nullptr) {
+           Prol<T> pr = Prol<T>(), const T* u = nullptr, DotOut* dot = nullptr) {
+  if constexpr (!std::is_same_v<T, double>) dot = nullptr;
   Level& L = h->lv[l];
   const Ell<T>& A = Prec<T>::A(L);
   Vecs<T>& v = Prec<T>::v(L);
@@ -204,6 +215,15 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
       // x is brought up to date on every other step (and on the last): a step that finds no
       // update pending leaves x alone and hands its own to the next step (16 bytes per row less)
       const bool defer = j < k && pending == 0.0 && !wpend.v && !pr.agg;
+      if constexpr (std::is_same_v<T, double>) {
+        if (dot && j == k && A.group == 1) {
+          AMGP_TRY(launch_fused_dot(s, 0, A, minv, g[cur], rsrc, x, alpha, c, w(j), pending,
+                                    step_weight(h, l, kind, k, j), wpend, pr, dot->r, dot->rold, dot->partial,
+                                    &dot->nb));
+          dot->done = true;
+          return AMG_OK;
+        }
+      }
       AMGP_TRY(launch_fused<T>(s, 0, j < k, A, minv, g[cur], g[1 - cur], rsrc, v.r, defer ? nullptr : x, alpha, c,
                                w(j), pending, step_weight(h, l, kind, k, j), wpend, pr));
       rsrc = v.r;
@@ -238,6 +258,14 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
   for (int j = j0; j <= k - 1; ++j) {
     const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
     const bool defer = j < k - 1 && pending == 0.0 && !pr.agg;  // as in the 4th kinds
+    if constexpr (std::is_same_v<T, double>) {
+      if (dot && j == k - 1 && A.group == 1) {
+        AMGP_TRY(launch_fused_dot(s, 1, A, minv, g[cur], v.r, x, rho * rho_prev, 2.0 * rho / delta, 1.0, pending,
+                                  Wt(), Wt(), pr, dot->r, dot->rold, dot->partial, &dot->nb));
+        dot->done = true;
+        return AMG_OK;
+      }
+    }
     AMGP_TRY(launch_fused<T>(s, 1, j < k - 1, A, minv, g[cur], g[1 - cur], v.r, v.r, defer ? nullptr : x,
                              rho * rho_prev, 2.0 * rho / delta, 1.0, pending, Wt(), Wt(), pr));
     pending = defer ? 1.0 : 0.0;
@@ -289,9 +317,11 @@ int prolong_set(Handle* h, int l, const T* yc, T* y, hipStream_t s) {
 
 constexpr int64_t kFusedTransferMaxRows = 1 << 20;
 
-// V-cycle of eq. (amg) from level l: x = B_l b.  u (optional): M^{-1} b for the pre-smoothing.
+// V-cycle of eq. (amg) from level l: x = B_l b.  u (optional): M^{-1} b for the pre-smoothing;
+// dot (optional): the CG's dot products of x, taken by the post-smoothing's last kernel.
 template <typename T>
-int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s, const T* u = nullptr) {
+int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s, const T* u = nullptr,
+           DotOut* dot = nullptr) {
   if (l == h->nlevels - 1) return coarse<T>(h, b, x, s);
   Level& L = h->lv[l];
   Vecs<T>& vc = Prec<T>::v(h->lv[l + 1]);
@@ -304,15 +334,15 @@ int vcycle(Handle* h, int l, int kind, int k, const T* b, T* x, hipStream_t s, c
   // every neighbour costs more than the pass it saves (43.4 vs 34.1 + 9.8 us on 2097152 rows,
   // 361 vs 284 + 59 us on 16777216), so they keep the separate prolongation.
   if (!L.general && kind != AMG_L1JAC && Prec<T>::A(L).group == 1 && L.n <= kFusedTransferMaxRows)
-    return smooth<T>(h, l, kind, k, b, x, false, s, nullptr, Prol<T>{L.agg, vc.x});
+    return smooth<T>(h, l, kind, k, b, x, false, s, nullptr, Prol<T>{L.agg, vc.x}, nullptr, dot);
   AMGP_TRY(prolong_add<T>(h, l, vc.x, x, s));
-  return smooth<T>(h, l, kind, k, b, x, false, s);
+  return smooth<T>(h, l, kind, k, b, x, false, s, nullptr, Prol<T>(), nullptr, dot);
 }
 
 // keep32 (FP32 hierarchy): leave the result in the level-0 float vector v32.x instead of
 // converting it into z (the CG kernels read it there).
 int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream_t s, bool keep32 = false,
-               const double* u = nullptr) {
+               const double* u = nullptr, DotOut* dot = nullptr) {
   if (h->precision == AMG_FP32) {
     Vecs<float>& v = h->lv[0].v32;
     AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
@@ -320,7 +350,7 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
     if (keep32) return AMG_OK;
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
-  return vcycle<double>(h, 0, kind, k, r, z, s, u);
+  return vcycle<double>(h, 0, kind, k, r, z, s, u, dot);
 }
 
 // The V-cycle as one HIP graph: captured on the handle's own stream the first
@@ -887,9 +917,15 @@ int precond_dot(Handle* h, int kind, int k, bool poly, int mode, const double* r
   const int64_t n = h->lv[0].n;
   const GraphEntry key{kind, k, mode, poly, r, z, rold, nullptr};  // u is fixed by (h, kind, k, mode)
   const float* z32 = cg_z32(h, poly);
+  DotOut d;
+  d.r = r;
+  d.rold = mode == RED_BETA_FLEX ? rold : nullptr;
+  d.partial = h->partial;
+  DotOut* dp = z32 ? nullptr : &d;  // FP64 results only
   return run_graph(h, key, s, [&](hipStream_t cs) {
-    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs, nullptr, Prol<double>(), u)
-                  : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr, u));
+    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs, nullptr, Prol<double>(), u, dp)
+                  : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr, u, dp));
+    if (d.done) return launch_reduce(cs, mode, d.nb, h->partial, h->scal, h->dflag);
     if (z32) return sum_dot<float>(h, cs, mode, r, z32, mode == RED_BETA_FLEX ? rold : nullptr,
                                    mode == RED_BETA_FLEX ? z32 : nullptr, n);
     if (mode == RED_BETA_FLEX) return sum_dot<double>(h, cs, mode, r, z, rold, z, n);
