@@ -144,14 +144,14 @@ def solve_bytes(levels, M0_64, w, kind, k, iters, flexible, u_path=False):
     one V-cycle (FP32: with the casts) and its dot products; the last x += alpha p after the loop.
     u_path: the r update also writes u = M^-1 r (reading M^-1), which the V-cycle's merged first
     two steps read in place of the gathered M^-1 and r (large 27-point FP64 fine levels).
-    FP64 hierarchies with a degree of at least 2 and more than one level take the dot products
-    of z inside the V-cycle's last kernel, which then reads r (and r_old) but not z again."""
+    Hierarchies with a degree of at least 2 and more than one level take the dot products of z
+    inside the V-cycle's last kernel, which then reads r (and r_old) but not z again."""
     n = levels[0][0]
     wz = w  # the CG kernels read the hierarchy's own output
     vc = vcycle_bytes(levels, w, kind, k) + (12 * n if w == 4 else 0)
     dots = (8 + wz) * n + (8 * n if flexible else 0)
-    if w == 8 and kind != 0 and k >= 2 and len(levels) > 1:
-        dots -= 8 * n
+    if kind != 0 and k >= 2 and len(levels) > 1:
+        dots -= wz * n
     per_it = (M0_64 + (24 + wz + 16) * n) + (24 + (8 if flexible else 0)) * n + vc + dots
     if u_path:
         per_it += 24 * n

@@ -247,9 +247,10 @@ bool first2_takes_u(const Ell<double>& A);
 // The last step of an application (as launch_fused with store = false) on a level of one lane per
 // row, with the block partials of (dr, x) and, with drold, of (drold, x) written as launch_dot2
 // writes them; AMG_EINVAL on levels of several lanes per row.
-int launch_fused_dot(hipStream_t s, int mode, const Ell<double>& A, const double* minv, const double* gold,
-                     const double* rin, double* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv,
-                     Prol<double> pr, const double* dr, const double* drold, double* partial, unsigned* nblocks);
+template <typename T>
+int launch_fused_dot(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* gold, const T* rin, T* x,
+                     double alpha, double c, double w, double wprev, Wt wv, Wt wpv, Prol<T> pr, const double* dr,
+                     const double* drold, double* partial, unsigned* nblocks);
 template <typename T>
 int launch_first_res(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* b, const T* x, T* r,
                      T* g, double c, Prol<T> pr = Prol<T>());  // pr: A.group must be 1

@@ -438,18 +438,17 @@ __global__ __launch_bounds__(kBlock) void k_fused_keep_x(int64_t n, EllView<T> A
 // END fused-step
 
 // The last step of an application with the CG's dot products of its result fused in: block
-// partials of (dr, x) and, with drold, of (drold, x), over the x this step stores.  The products,
-// the block order and the sums are those of k_dot2 on the same grid, so the partials are the same
-// numbers.
-template <int MODE, bool NT, bool W>
-__global__ __launch_bounds__(kBlock) void k_fused_dot(int64_t n, EllView<double> A, const double* __restrict__ minv,
-                                                      const double* __restrict__ gold, const double* rin,
-                                                      double* __restrict__ x, double alpha, double c, double w,
-                                                      double wprev, Wt wv, Wt wpv, Prol<double> pr,
+// partials of (dr, x) and, with drold, of (drold, x), over the x this step stores (an FP32 x is
+// converted exactly).  The products, the block order and the sums are those of k_dot2 on the
+// same grid, so the partials are the same numbers.
+template <typename T, int MODE, bool NT, bool W>
+__global__ __launch_bounds__(kBlock) void k_fused_dot(int64_t n, EllView<T> A, const T* __restrict__ minv,
+                                                      const T* __restrict__ gold, const T* rin, T* __restrict__ x,
+                                                      T alpha, T c, T w, T wprev, Wt wv, Wt wpv, Prol<T> pr,
                                                       const double* __restrict__ dr, const double* __restrict__ drold,
                                                       double* __restrict__ partial) {
-  const double xn = fused_step<double, MODE, false, NT, 1, true, W>(n, A, minv, gold, nullptr, rin, nullptr, x, alpha,
-                                                                     c, w, wprev, wv, wpv, pr);
+  const double xn = (double)fused_step<T, MODE, false, NT, 1, true, W>(n, A, minv, gold, nullptr, rin, nullptr, x,
+                                                                        alpha, c, w, wprev, wv, wpv, pr);
   const int64_t i = row_index();
   double v = 0.0, u = 0.0;
   if (i < n) {
@@ -1286,31 +1285,40 @@ int launch_fused(hipStream_t s, int mode, bool store, const Ell<T>& A, const T* 
   });
 }
 
-int launch_fused_dot(hipStream_t s, int mode, const Ell<double>& A, const double* minv, const double* gold,
-                     const double* rin, double* x, double alpha, double c, double w, double wprev, Wt wv, Wt wpv,
-                     Prol<double> pr, const double* dr, const double* drold, double* partial, unsigned* nblocks) {
+template <typename T>
+int launch_fused_dot(hipStream_t s, int mode, const Ell<T>& A, const T* minv, const T* gold, const T* rin, T* x,
+                     double alpha, double c, double w, double wprev, Wt wv, Wt wpv, Prol<T> pr, const double* dr,
+                     const double* drold, double* partial, unsigned* nblocks) {
   if (A.group != 1) return AMG_EINVAL;
   const dim3 gr(xcd_grid(A.n)), bl(kBlock);
   auto go = [&](auto nt, auto wd) {
     constexpr bool NT = decltype(nt)::value, W = decltype(wd)::value;
     if (mode == 0)
-      hipLaunchKernelGGL((k_fused_dot<0, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, alpha, c, w, wprev,
-                         wv, wpv, pr, dr, drold, partial);
+      hipLaunchKernelGGL((k_fused_dot<T, 0, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, (T)alpha, (T)c,
+                         (T)w, (T)wprev, wv, wpv, pr, dr, drold, partial);
     else
-      hipLaunchKernelGGL((k_fused_dot<1, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, alpha, c, w, wprev,
-                         wv, wpv, pr, dr, drold, partial);
+      hipLaunchKernelGGL((k_fused_dot<T, 1, NT, W>), gr, bl, 0, s, A.n, view(A), minv, gold, rin, x, (T)alpha, (T)c,
+                         (T)w, (T)wprev, wv, wpv, pr, dr, drold, partial);
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
+  bool wd = false;
+  if constexpr (std::is_same_v<T, double>) wd = wide(A);  // the wide batches are FP64 only, as in launch_fused
   if (!streamed(gr.x))
     go(F_(), F_());
-  else if (wide(A))
-    go(T_(), T_());
+  else if (wd)
+    go(T_(), std::integral_constant<bool, std::is_same_v<T, double>>());
   else
     go(T_(), F_());
   *nblocks = gr.x;
   return LAUNCH_OK();
 }
+template int launch_fused_dot<double>(hipStream_t, int, const Ell<double>&, const double*, const double*,
+                                      const double*, double*, double, double, double, double, Wt, Wt, Prol<double>,
+                                      const double*, const double*, double*, unsigned*);
+template int launch_fused_dot<float>(hipStream_t, int, const Ell<float>&, const float*, const float*, const float*,
+                                     float*, double, double, double, double, Wt, Wt, Prol<float>, const double*,
+                                     const double*, double*, unsigned*);
 
 template <typename T>
 int launch_jacobi(hipStream_t s, const Ell<T>& A, const T* minv, const T* b, const T* xold, T* xnew) {

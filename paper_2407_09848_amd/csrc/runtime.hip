@@ -150,11 +150,10 @@ struct DotOut {
 // pr (optional, x_in != 0, Chebyshev kinds, one row per lane): the smoother runs on
 // x_in + P x_c, the box prolongation being applied inside its first two kernels.
 // u (optional, x = 0): M^{-1} b, written by the kernel that produced b, for the merged first
-// two steps.  dot (optional, FP64): the dot products of the result, see DotOut.
+// two steps.  dot (optional): the dot products of the result, see DotOut.
 template <typename T>
 int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStream_t s, T* r0_copy = nullptr,
            Prol<T> pr = Prol<T>(), const T* u = nullptr, DotOut* dot = nullptr) {
-  if constexpr (!std::is_same_v<T, double>) dot = nullptr;
   Level& L = h->lv[l];
   const Ell<T>& A = Prec<T>::A(L);
   Vecs<T>& v = Prec<T>::v(L);
@@ -215,14 +214,12 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
       // x is brought up to date on every other step (and on the last): a step that finds no
       // update pending leaves x alone and hands its own to the next step (16 bytes per row less)
       const bool defer = j < k && pending == 0.0 && !wpend.v && !pr.agg;
-      if constexpr (std::is_same_v<T, double>) {
-        if (dot && j == k && A.group == 1) {
-          AMGP_TRY(launch_fused_dot(s, 0, A, minv, g[cur], rsrc, x, alpha, c, w(j), pending,
-                                    step_weight(h, l, kind, k, j), wpend, pr, dot->r, dot->rold, dot->partial,
-                                    &dot->nb));
-          dot->done = true;
-          return AMG_OK;
-        }
+      if (dot && j == k && A.group == 1) {
+        AMGP_TRY(launch_fused_dot<T>(s, 0, A, minv, g[cur], rsrc, x, alpha, c, w(j), pending,
+                                     step_weight(h, l, kind, k, j), wpend, pr, dot->r, dot->rold, dot->partial,
+                                     &dot->nb));
+        dot->done = true;
+        return AMG_OK;
       }
       AMGP_TRY(launch_fused<T>(s, 0, j < k, A, minv, g[cur], g[1 - cur], rsrc, v.r, defer ? nullptr : x, alpha, c,
                                w(j), pending, step_weight(h, l, kind, k, j), wpend, pr));
@@ -258,13 +255,11 @@ int smooth(Handle* h, int l, int kind, int k, const T* b, T* x, bool xz, hipStre
   for (int j = j0; j <= k - 1; ++j) {
     const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
     const bool defer = j < k - 1 && pending == 0.0 && !pr.agg;  // as in the 4th kinds
-    if constexpr (std::is_same_v<T, double>) {
-      if (dot && j == k - 1 && A.group == 1) {
-        AMGP_TRY(launch_fused_dot(s, 1, A, minv, g[cur], v.r, x, rho * rho_prev, 2.0 * rho / delta, 1.0, pending,
-                                  Wt(), Wt(), pr, dot->r, dot->rold, dot->partial, &dot->nb));
-        dot->done = true;
-        return AMG_OK;
-      }
+    if (dot && j == k - 1 && A.group == 1) {
+      AMGP_TRY(launch_fused_dot<T>(s, 1, A, minv, g[cur], v.r, x, rho * rho_prev, 2.0 * rho / delta, 1.0, pending,
+                                   Wt(), Wt(), pr, dot->r, dot->rold, dot->partial, &dot->nb));
+      dot->done = true;
+      return AMG_OK;
     }
     AMGP_TRY(launch_fused<T>(s, 1, j < k - 1, A, minv, g[cur], g[1 - cur], v.r, v.r, defer ? nullptr : x,
                              rho * rho_prev, 2.0 * rho / delta, 1.0, pending, Wt(), Wt(), pr));
@@ -346,7 +341,7 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
   if (h->precision == AMG_FP32) {
     Vecs<float>& v = h->lv[0].v32;
     AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
-    AMGP_TRY(vcycle<float>(h, 0, kind, k, v.b, v.x, s));
+    AMGP_TRY(vcycle<float>(h, 0, kind, k, v.b, v.x, s, nullptr, dot));
     if (keep32) return AMG_OK;
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
@@ -921,10 +916,9 @@ int precond_dot(Handle* h, int kind, int k, bool poly, int mode, const double* r
   d.r = r;
   d.rold = mode == RED_BETA_FLEX ? rold : nullptr;
   d.partial = h->partial;
-  DotOut* dp = z32 ? nullptr : &d;  // FP64 results only
   return run_graph(h, key, s, [&](hipStream_t cs) {
-    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs, nullptr, Prol<double>(), u, dp)
-                  : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr, u, dp));
+    AMGP_TRY(poly ? smooth<double>(h, 0, kind, k, r, z, true, cs, nullptr, Prol<double>(), u, &d)
+                  : vcycle_top(h, kind, k, r, z, cs, z32 != nullptr, u, &d));
     if (d.done) return launch_reduce(cs, mode, d.nb, h->partial, h->scal, h->dflag);
     if (z32) return sum_dot<float>(h, cs, mode, r, z32, mode == RED_BETA_FLEX ? rold : nullptr,
                                    mode == RED_BETA_FLEX ? z32 : nullptr, n);
