@@ -136,7 +136,6 @@ inline Wt step_weight(const Handle* h, int l, int kind, int k, int j) {
   return w;
 }
 
-// r0_copy (optional, x_in != 0 only): receives r^(0) = b - A x_in, the input of the recurrence.
 // The CG's dot products of a preconditioner result with r (and, flexible, r_old), taken by the
 // preconditioner's last kernel when that kernel is a recurrence step (done is then set).
 struct DotOut {
@@ -147,6 +146,7 @@ struct DotOut {
   bool done = false;
 };
 
+// r0_copy (optional, x_in != 0 only): receives r^(0) = b - A x_in, the input of the recurrence.
 // pr (optional, x_in != 0, Chebyshev kinds, one row per lane): the smoother runs on
 // x_in + P x_c, the box prolongation being applied inside its first two kernels.
 // u (optional, x = 0): M^{-1} b, written by the kernel that produced b, for the merged first
