@@ -244,6 +244,9 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
                        Wt w2v = Wt(), const T* u = nullptr);
 // u = M^{-1} b, given to launch_first2_zero, is read on these levels (and ignored on the others)
 bool first2_takes_u(const Ell<double>& A);
+bool first2_takes_u(const Ell<float>& A);
+// b = (float) r and u = M^{-1} b for an FP32 fine level whose merged first two steps take u
+int launch_cast_u(hipStream_t s, int64_t n, const double* r, const float* minv, float* b, float* u);
 // The last step of an application (as launch_fused with store = false) on a level of one lane per
 // row, with the block partials of (dr, x) and, with drold, of (drold, x) written as launch_dot2
 // writes them; AMG_EINVAL on levels of several lanes per row.

@@ -819,6 +819,19 @@ __global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restric
   y[i] = (Tout)x[i];
 }
 
+// b = (float) r and u = M^{-1} b, the products the merged first two steps form for their gathered
+// neighbours (an FP32 hierarchy's fine level, read by k_first2_zero<..., U>)
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_cast_u(int64_t n, const double* __restrict__ r,
+                                                   const float* __restrict__ minv, float* __restrict__ b,
+                                                   float* __restrict__ u) {
+  const int64_t i = row_index();
+  if (i >= n) return;
+  const float bi = (float)ld<NT>(r + i);
+  b[i] = bi;
+  u[i] = minv[i] * bi;
+}
+
 // ---------------------------------------------------------------------------
 // CG kernels (float64): fused SpMV + dot, update + dot, and a single-block
 // second-stage reduction that also forms the CG scalars on the device.
@@ -1066,6 +1079,9 @@ inline bool wide(const Ell<double>& A) {
 
 // The levels whose merged first two steps can read u = M^{-1} b instead of gathering M^{-1} and b
 bool first2_takes_u(const Ell<double>& A) { return streamed(xcd_grid(A.n)) && wide(A); }
+bool first2_takes_u(const Ell<float>& A) {
+  return streamed(xcd_grid(A.n)) && A.doff && A.group == 1 && A.padded >= (int64_t)kWideMinSteps * A.n;
+}
 
 // Runs f(std::integral_constant<int, G>) for the matrix's lanes per row G.
 template <typename F>
@@ -1173,6 +1189,10 @@ int launch_first2_zero(hipStream_t s, int mode, bool store, const Ell<T>& A, con
                                                (T)alpha, (T)c, (T)w1, (T)w2, w1v, w2v);
             return;
           }
+        } else if (u) {
+          go_first2_zero<T, true, 1, false, true>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1,
+                                                  (T)alpha, (T)c, (T)w1, (T)w2, w1v, w2v, u);
+          return;
         }
         go_first2_zero<T, true, 1>(gr, s, mode, store, view(A), A.n, minv, b, gnew, r, x, (T)c1, (T)alpha, (T)c,
                                    (T)w1, (T)w2, w1v, w2v);
@@ -1410,6 +1430,15 @@ int launch_fill(hipStream_t s, int64_t n, T v, T* y) {
 template <typename Tin, typename Tout>
 int launch_cast(hipStream_t s, int64_t n, const Tin* x, Tout* y) {
   hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(xcd_grid(n)), dim3(kBlock), 0, s, n, x, y);
+  return LAUNCH_OK();
+}
+
+int launch_cast_u(hipStream_t s, int64_t n, const double* r, const float* minv, float* b, float* u) {
+  const unsigned g = xcd_grid(n);
+  if (streamed(g))
+    hipLaunchKernelGGL(k_cast_u<true>, dim3(g), dim3(kBlock), 0, s, n, r, minv, b, u);
+  else
+    hipLaunchKernelGGL(k_cast_u<false>, dim3(g), dim3(kBlock), 0, s, n, r, minv, b, u);
   return LAUNCH_OK();
 }
 

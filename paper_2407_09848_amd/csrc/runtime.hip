@@ -340,8 +340,16 @@ int vcycle_top(Handle* h, int kind, int k, const double* r, double* z, hipStream
                const double* u = nullptr, DotOut* dot = nullptr) {
   if (h->precision == AMG_FP32) {
     Vecs<float>& v = h->lv[0].v32;
-    AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
-    AMGP_TRY(vcycle<float>(h, 0, kind, k, v.b, v.x, s, nullptr, dot));
+    // on large 27-point levels the conversion of r also writes u = M^{-1} b for the merged first
+    // two steps (the handle's FP64 u vector is free with an FP32 hierarchy)
+    float* u32 = kind != AMG_L1JAC && k >= 2 && h->nlevels > 1 && first2_takes_u(h->lv[0].A32)
+                     ? reinterpret_cast<float*>(h->cg_u)
+                     : nullptr;
+    if (u32)
+      AMGP_TRY(launch_cast_u(s, h->lv[0].n, r, v.minv, v.b, u32));
+    else
+      AMGP_TRY((launch_cast<double, float>(s, h->lv[0].n, r, v.b)));
+    AMGP_TRY(vcycle<float>(h, 0, kind, k, v.b, v.x, s, u32, dot));
     if (keep32) return AMG_OK;
     return launch_cast<float, double>(s, h->lv[0].n, v.x, z);
   }
