@@ -223,6 +223,12 @@ def true_relres(amg, h, bd, x):
     return float(torch.linalg.norm(bd - y) / torch.linalg.norm(bd))
 
 
+def rel_to(x, ref):
+    """||x - ref|| / ||ref||: a variant's solution against the FP64 headline solve's."""
+    import torch
+    return float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+
+
 def ceiling(amg, stream):
     """Plain read and copy of this GPU through the library's bandwidth kernels (16-byte
     nontemporal accesses): a 4 GiB read, a 2 GiB -> 2 GiB copy."""
@@ -308,7 +314,7 @@ def heldout_loss(amg, learned, h, b, params, deg, sigmas):
     return {"loss_plain": round(lp, 6), "loss_learned": round(ll, 6), "fallback_rows": learned.count_fallbacks(valid)}
 
 
-def learned_variant(args, amg, W, h, bd, x, stream, params):
+def learned_variant(args, amg, W, h, bd, x, stream, params, x_ref):
     """Apply the trained network per level to this hierarchy; the learned weights are kept
     when they lower the two-cycle residual ratio of this right-hand side (else the plain
     weights: the fallback); time the solve."""
@@ -328,7 +334,8 @@ def learned_variant(args, amg, W, h, bd, x, stream, params):
     tm, (rc, itv, _, _) = event_time(stream, lambda: amg.pcg_solve(h, args.kind, deg, bd, x, True, 1e-8, 1000), 2)
     rr = true_relres(amg, h, bd, x)
     amg.amg_reset_beta(h)
-    return {"ms": round(tm, 3), "iters": itv, "true_relres": rr, "weights": "learned" if use else "plain (fallback)",
+    return {"ms": round(tm, 3), "iters": itv, "true_relres": rr, "vs_fp64_headline_solution": rel_to(x, x_ref),
+            "weights": "learned" if use else "plain (fallback)",
             "two_cycle_ratio_plain": round(r_plain, 6), "two_cycle_ratio_learned": round(r_learned, 6),
             "level_betas": [[round(v, 6) for v in row] for row in lb]}
 
@@ -603,7 +610,8 @@ def main():
     for kind in other_kinds:
         tm, itv = time_solve(h, kind, args.degree)
         variants[f"fp64_{KIND_NAMES[kind]}_k{args.degree}"] = {"ms": round(tm, 3), "iters": itv,
-                                                              "true_relres": true_relres(amg, h, bd, x)}
+                                                              "true_relres": true_relres(amg, h, bd, x),
+                                                              "vs_fp64_headline_solution": rel_to(x, x_head)}
     progress("other smoother kinds done")
     if "fp32" in chosen:
         t0 = time.perf_counter()
@@ -613,7 +621,7 @@ def main():
         tm, itv = time_solve(h32, args.kind, args.degree, flexible=True)
         variants[f"fp32_{KIND_NAMES[args.kind]}_k{args.degree}"] = {
             "ms": round(tm, 3), "iters": itv, "setup_s": round(s32, 3), "outer": "FP64 flexible CG",
-            "true_relres": true_relres(amg, h, bd, x)}
+            "true_relres": true_relres(amg, h, bd, x), "vs_fp64_headline_solution": rel_to(x, x_head)}
         # the FP32 hierarchy's fine-level fused step (k_fused<float,...>), timed as the headline's
         b32 = bd.float()
         x32 = torch.zeros(n0, dtype=torch.float32, device="cuda")
@@ -647,7 +655,7 @@ def main():
     if "learned" in chosen and args.kind == 2:
         params, learned_info = train_learned(args, amg, W)
         variants[f"learned_{KIND_NAMES[args.kind]}_k{args.degree}"] = learned_variant(args, amg, W, h, bd, x,
-                                                                                    stream, params)
+                                                                                    stream, params, x_head)
         progress("learned weights done")
     for v in variants.values():
         v["vs_plain_fp64"] = round(v["ms"] / base, 3)
