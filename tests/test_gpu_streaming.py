@@ -166,22 +166,23 @@ def test_streaming_27pt_pcg_smoother_iterates(p27):
     """CG preconditioned by the fine-level smoother alone on the 27-point level: from the second
     iteration on, its residual update also writes u = M^-1 r, which the smoother's merged first
     two steps read in place of the gathered M^-1 and r.  The iterate after three iterations
-    matches the oracle's CG iterate (kinds 1-3, degree 4)."""
+    matches the oracle's CG iterate (kinds 1-3, degree 4; the optimal 4th kind also in the
+    flexible CG, whose dot products take r_old as well)."""
     torch = torch_cuda()
     import paper_2407_09848_amd as amg
     pr = p27
     errs = []
     with hierarchy(pr.A) as h:
-        for kind in (1, 2, 3):
+        for kind, flex in ((1, False), (2, False), (3, False), (2, True)):
             beta, a = oracle_params(kind, 4)
             x = nan_vec(pr.A.n)
-            rc, it, rel, _ = amg.pcg_solve_smoother(h, kind, 4, dev(pr.b), x, True, 1e-14, 3)
+            rc, it, rel, _ = amg.pcg_solve_smoother(h, kind, 4, dev(pr.b), x, True, 1e-14, 3, flex)
             torch.cuda.synchronize()
-            ro = OA.pcg(pr.As, pr.b, lambda r: S.smooth(pr.As, pr.Minv, r, None, kind, 4, beta, a), 1e-14, 3)
-            assert rc == amg.AMG_NOT_CONVERGED and it == 3 == ro.iters, kind
-            assert rel == pytest.approx(ro.relres, rel=1e-9), kind
+            ro = OA.pcg(pr.As, pr.b, lambda r: S.smooth(pr.As, pr.Minv, r, None, kind, 4, beta, a), 1e-14, 3, flex)
+            assert rc == amg.AMG_NOT_CONVERGED and it == 3 == ro.iters, (kind, flex)
+            assert rel == pytest.approx(ro.relres, rel=1e-9), (kind, flex)
             errs.append(relerr(host(x), ro.x))
-            assert errs[-1] <= 1e-10, (kind, errs[-1])
+            assert errs[-1] <= 1e-10, (kind, flex, errs[-1])
     _log(f"27-point 164^3 smoother-preconditioned CG: max error {max(errs):.2e}")
 
 
