@@ -308,10 +308,25 @@ enum ReduceMode { RED_BB = 0, RED_RZ0, RED_ALPHA, RED_RR, RED_BETA, RED_BETA_FLE
 int launch_check_finite(hipStream_t s, int64_t n, const double* x, int* flag);
 
 // ---- differentiable V-cycle and learned-beta network (kernels_train.hip) ----
-// out[p * ostride] (+)= (a_p, b_p) over segment p (b = nullptr: |a_p|^2); partial >= 64 * nseg doubles
+// out[p * ostride] (+)= (a_p, b_p) over segment p (b = nullptr: |a_p|^2); partial >= kSegBlocks * nseg
+// doubles
+constexpr int kSegBlocks = 64;  // blocks per problem segment in a segmented reduction
 template <typename T>
 int launch_seg_dot(hipStream_t s, int nseg, int64_t rpp, const T* a, const T* b, double* partial, double* out,
                    int ostride, bool acc);
+// The per-problem sums of a segmented dot product's block partials, left to a later kernel.
+struct SegFin {
+  const double* partial = nullptr;
+  double* out = nullptr;
+  int nseg = 0, ostride = 0, acc = 0;
+};
+// The block partials of (a_p, b_p) into partial, with the pending sums prev (nseg <= 256) done
+// first by the kernel's first block; the caller keeps {partial, out, nseg, ostride, acc} as the
+// next pending sums and must not reuse partial before they are done.
+template <typename T>
+int launch_seg_dot_chain(hipStream_t s, int nseg, int64_t rpp, const T* a, const T* b, double* partial,
+                         SegFin prev);
+int launch_seg_finish(hipStream_t s, SegFin f);  // the pending sums alone (none: nothing)
 template <typename T>
 int launch_loss_seed(hipStream_t s, int64_t n, int64_t rpp, int P, const double* sq, const T* r2, T* g);
 int launch_loss_value(hipStream_t s, int P, const double* sq, double* out);

@@ -14,7 +14,6 @@ namespace amgp {
 
 namespace {
 
-constexpr int kSegBlocks = 64;  // blocks per problem segment in a segmented reduction
 
 template <typename T>
 __device__ __forceinline__ double wave_block_sum(double v, double* sm) {
@@ -30,9 +29,20 @@ __device__ __forceinline__ double wave_block_sum(double v, double* sm) {
 
 // partial[p][bx] = sum over rows of segment p handled by block bx of a_i * b_i
 // (b = nullptr: a_i^2).  grid = (kSegBlocks, nseg).
+// out[p * ostride] (+)= sum_bx partial[p][bx]   (accumulate when acc != 0)
+__device__ __forceinline__ void seg_finish_one(int p, const double* __restrict__ partial, double* __restrict__ out,
+                                               int ostride, int acc) {
+  double s = 0.0;
+  for (int i = 0; i < kSegBlocks; ++i) s += partial[p * kSegBlocks + i];
+  out[(int64_t)p * ostride] = acc ? out[(int64_t)p * ostride] + s : s;
+}
+
+// prev: the pending per-problem sums of an earlier call, done first by block (0, 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_seg_dot(int64_t rpp, const T* __restrict__ a, const T* __restrict__ b,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial, SegFin prev) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < prev.nseg)
+    seg_finish_one(threadIdx.x, prev.partial, prev.out, prev.ostride, prev.acc);
   __shared__ double sm[kBlock / kWave];
   const int p = blockIdx.y;
   const T* ap = a + (int64_t)p * rpp;
@@ -46,14 +56,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_dot(int64_t rpp, const T* __rest
   if (threadIdx.x == 0) partial[p * kSegBlocks + blockIdx.x] = s;
 }
 
-// out[p * ostride] (+)= sum_bx partial[p][bx]   (accumulate when acc != 0)
 __global__ void k_seg_finish(int nseg, const double* __restrict__ partial, double* __restrict__ out, int ostride,
                              int acc) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nseg) return;
-  double s = 0.0;
-  for (int i = 0; i < kSegBlocks; ++i) s += partial[p * kSegBlocks + i];
-  out[(int64_t)p * ostride] = acc ? out[(int64_t)p * ostride] + s : s;
+  seg_finish_one(p, partial, out, ostride, acc);
 }
 
 // Loss seed: loss = mean_p ||r2_p|| / ||r0_p||; g = d loss / d r2 = r2_p / (P ||r2_p|| ||r0_p||).
@@ -318,8 +325,23 @@ __global__ __launch_bounds__(kBlock) void k_offdiag_ratio(int64_t n, const int32
 template <typename T>
 int launch_seg_dot(hipStream_t s, int nseg, int64_t rpp, const T* a, const T* b, double* partial, double* out,
                    int ostride, bool acc) {
-  hipLaunchKernelGGL(k_seg_dot<T>, dim3(kSegBlocks, nseg), dim3(kBlock), 0, s, rpp, a, b, partial);
+  hipLaunchKernelGGL(k_seg_dot<T>, dim3(kSegBlocks, nseg), dim3(kBlock), 0, s, rpp, a, b, partial, SegFin());
   hipLaunchKernelGGL(k_seg_finish, dim3((nseg + 63) / 64), dim3(64), 0, s, nseg, partial, out, ostride, acc ? 1 : 0);
+  return LAUNCH_OK();
+}
+
+template <typename T>
+int launch_seg_dot_chain(hipStream_t s, int nseg, int64_t rpp, const T* a, const T* b, double* partial,
+                         SegFin prev) {
+  if (prev.nseg > kBlock) return AMG_EINVAL;
+  hipLaunchKernelGGL(k_seg_dot<T>, dim3(kSegBlocks, nseg), dim3(kBlock), 0, s, rpp, a, b, partial, prev);
+  return LAUNCH_OK();
+}
+
+int launch_seg_finish(hipStream_t s, SegFin f) {
+  if (f.nseg == 0) return AMG_OK;
+  hipLaunchKernelGGL(k_seg_finish, dim3((f.nseg + 63) / 64), dim3(64), 0, s, f.nseg, f.partial, f.out, f.ostride,
+                     f.acc);
   return LAUNCH_OK();
 }
 
@@ -443,6 +465,7 @@ int launch_offdiag_ratio(hipStream_t s, int64_t n, const int32_t* ptr, const int
 
 #define INST_T(T)                                                                                          \
   template int launch_seg_dot<T>(hipStream_t, int, int64_t, const T*, const T*, double*, double*, int, bool); \
+  template int launch_seg_dot_chain<T>(hipStream_t, int, int64_t, const T*, const T*, double*, SegFin);     \
   template int launch_loss_seed<T>(hipStream_t, int64_t, int64_t, int, const double*, const T*, T*);         \
   template int launch_neg<T>(hipStream_t, int64_t, const T*, T*);                                           \
   template int launch_prolong_set<T>(hipStream_t, int64_t, const int32_t*, const T*, T*);                   \

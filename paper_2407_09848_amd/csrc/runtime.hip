@@ -521,10 +521,28 @@ int smooth_adjoint(Handle* h, int l, int k, const T* v, T* u, const T* r0, doubl
   const int stride = h->nlevels * k;
   T* g[2] = {vv.g0, vv.g1};
   int cur = 0;
+  // gbeta[.][l][j-1] += <z_j, r0>: each dot's per-problem sums are done by the next dot's first
+  // block (the same sums in the same order), its partials alternating between the two halves
+  // of the partial buffer; the last ones by a kernel of their own
+  const bool chain = h->nbatch <= kBlock;
+  SegFin pending;
+  int half = 0;
+  auto seg_dot = [&](const T* z, double* out) -> int {
+    if (!chain) return launch_seg_dot<T>(s, h->nbatch, rpp, z, r0, h->tr_partial, out, stride, true);
+    double* part = h->tr_partial + (size_t)half * kSegBlocks * h->nbatch;
+    AMGP_TRY(launch_seg_dot_chain<T>(s, h->nbatch, rpp, z, r0, part, pending));
+    pending.partial = part;
+    pending.out = out;
+    pending.nseg = h->nbatch;
+    pending.ostride = stride;
+    pending.acc = 1;
+    half = 1 - half;
+    return AMG_OK;
+  };
   const double c1 = (8.0 * 1 - 4.0) / (2.0 * 1 + 1.0);
   AMGP_TRY(launch_first_zero<T>(s, 0, true, n, vv.minv, v, g[cur], nullptr, u, c1, h->beta_at(l, k, 0),
                                 step_weight(h, l, AMG_OPTCHEB4, k, 1)));
-  AMGP_TRY(launch_seg_dot<T>(s, h->nbatch, rpp, g[cur], r0, h->tr_partial, gbeta + (size_t)l * k, stride, true));
+  AMGP_TRY(seg_dot(g[cur], gbeta + (size_t)l * k));
   const T* rsrc = v;
   for (int j = 2; j <= k; ++j) {
     const double alpha = (2.0 * j - 3.0) / (2.0 * j + 1.0);
@@ -533,10 +551,9 @@ int smooth_adjoint(Handle* h, int l, int k, const T* v, T* u, const T* r0, doubl
                              h->beta_at(l, k, j - 1), 0.0, step_weight(h, l, AMG_OPTCHEB4, k, j), Wt()));
     rsrc = vv.r;
     cur = 1 - cur;
-    AMGP_TRY(launch_seg_dot<T>(s, h->nbatch, rpp, g[cur], r0, h->tr_partial, gbeta + (size_t)l * k + (j - 1),
-                               stride, true));
+    AMGP_TRY(seg_dot(g[cur], gbeta + (size_t)l * k + (j - 1)));
   }
-  return AMG_OK;
+  return launch_seg_finish(s, pending);
 }
 
 template <typename T>
